@@ -1,0 +1,214 @@
+"""CPU oracle for Metropolis-family resampling (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. The product path (the HIP library and
+its Python binding) never imports, links or calls it.
+
+``mgp_oracle.c`` holds the arithmetic; this module builds it with gcc and wraps
+it with ctypes. See the C file for the definitions and their sources in the
+paper (Algorithms 2-5, eq. (proposition)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mgp_oracle.c")
+LIB = os.path.join(HERE, "libmgp_oracle.so")
+
+METROPOLIS, C1, C2, MEGOPOLIS = 0, 1, 2, 3
+VARIANTS = {"metropolis": METROPOLIS, "c1": C1, "c2": C2, "megopolis": MEGOPOLIS}
+
+OK, EINVAL, ERANGE, EWEIGHTS = 0, -1, -2, -6
+
+CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``mgp_oracle.c`` into ``libmgp_oracle.so`` (single-threaded, no fast-math)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"], check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.mgp_oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.mgp_oracle_philox4x32_10.restype = None
+        L.mgp_oracle_draw_u.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.mgp_oracle_draw_u.restype = ctypes.c_float
+        L.mgp_oracle_offset.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.mgp_oracle_offset.restype = ctypes.c_uint32
+        L.mgp_oracle_offsets.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u32p]
+        L.mgp_oracle_offsets.restype = None
+        L.mgp_oracle_megopolis_index.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.mgp_oracle_megopolis_index.restype = ctypes.c_uint32
+        L.mgp_oracle_resample.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                                          ctypes.c_uint32, ctypes.c_uint32, _u32p, _i32p, _u64p]
+        L.mgp_oracle_resample.restype = ctypes.c_int
+        L.mgp_oracle_resample_subset.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
+                                                 ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u32p,
+                                                 _i32p, ctypes.c_int32, _i32p]
+        L.mgp_oracle_resample_subset.restype = ctypes.c_int
+        L.mgp_oracle_trace.argtypes = [ctypes.c_int32, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                                       ctypes.c_uint32, ctypes.c_uint32, _u32p, ctypes.c_int32, _u32p, _f32p]
+        L.mgp_oracle_trace.restype = ctypes.c_int
+        L.mgp_oracle_reduce.argtypes = [_f32p, ctypes.c_int32, _f32p, _f64p]
+        L.mgp_oracle_reduce.restype = ctypes.c_int
+        L.mgp_oracle_choose_B.argtypes = [ctypes.c_double, ctypes.c_float, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_uint32, _u32p, _f64p, ctypes.POINTER(ctypes.c_int)]
+        L.mgp_oracle_choose_B.restype = ctypes.c_int
+        L.mgp_oracle_gather.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32, _f32p]
+        L.mgp_oracle_gather.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} returned {code}")
+        self.code = code
+
+
+def _variant(v) -> int:
+    return VARIANTS[v] if isinstance(v, str) else int(v)
+
+
+def philox4x32_10(counter, key) -> np.ndarray:
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().mgp_oracle_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+    return out
+
+
+def draw_u(seed: int, stream_id: int, i: int, b: int) -> np.float32:
+    return np.float32(lib().mgp_oracle_draw_u(seed, stream_id, i, b))
+
+
+def offsets(seed: int, stream_id: int, n: int, B: int) -> np.ndarray:
+    o = np.zeros(max(B, 1), dtype=np.uint32)
+    lib().mgp_oracle_offsets(seed, stream_id, n, B, _ptr(o, _u32p))
+    return o[:B]
+
+
+def megopolis_index(i: int, o: int, n: int) -> int:
+    return int(lib().mgp_oracle_megopolis_index(i, o, n))
+
+
+@dataclass
+class Stats:
+    w_max: float
+    w_sum: float
+    status: int
+
+
+def reduce(w: np.ndarray) -> Stats:
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    mx = ctypes.c_float()
+    s = ctypes.c_double()
+    rc = lib().mgp_oracle_reduce(_ptr(w, _f32p), w.size, ctypes.byref(mx), ctypes.byref(s))
+    if rc == EINVAL:
+        raise OracleError(rc, "mgp_oracle_reduce")
+    return Stats(float(mx.value), float(s.value), rc)
+
+
+def choose_B(w_sum: float, w_max: float, n: int, eps: float, b_max: int = 65536):
+    """Returns (B, raw, clamped)."""
+    B = ctypes.c_uint32()
+    raw = ctypes.c_double()
+    cl = ctypes.c_int()
+    rc = lib().mgp_oracle_choose_B(w_sum, w_max, n, eps, b_max, ctypes.byref(B), ctypes.byref(raw),
+                                   ctypes.byref(cl))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_choose_B")
+    return int(B.value), float(raw.value), bool(cl.value)
+
+
+def B_from_weights(w: np.ndarray, eps: float, b_max: int = 65536):
+    st = reduce(w)
+    if st.status:
+        raise OracleError(st.status, "mgp_oracle_reduce")
+    return choose_B(st.w_sum, st.w_max, w.size, eps, b_max)
+
+
+def resample(w: np.ndarray, variant, B: int, seed: int, stream_id: int = 0, partition_bytes: int = 128,
+             return_accepts: bool = False):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    n = w.size
+    v = _variant(variant)
+    anc = np.empty(n, dtype=np.int32)
+    scratch = np.zeros(max(B, 1), dtype=np.uint32)
+    acc = ctypes.c_uint64()
+    rc = lib().mgp_oracle_resample(_ptr(w, _f32p), n, v, B, seed, stream_id, partition_bytes,
+                                   _ptr(scratch, _u32p), _ptr(anc, _i32p), ctypes.byref(acc))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_resample")
+    if return_accepts:
+        return anc, int(acc.value)
+    return anc
+
+
+def resample_subset(w: np.ndarray, variant, B: int, seed: int, idx, stream_id: int = 0,
+                    partition_bytes: int = 128) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.empty(idx.size, dtype=np.int32)
+    scratch = np.zeros(max(B, 1), dtype=np.uint32)
+    rc = lib().mgp_oracle_resample_subset(_ptr(w, _f32p), w.size, _variant(variant), B, seed, stream_id,
+                                          partition_bytes, _ptr(scratch, _u32p), _ptr(idx, _i32p), idx.size,
+                                          _ptr(out, _i32p))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_resample_subset")
+    return out
+
+
+def trace(n: int, variant, B: int, seed: int, i: int, stream_id: int = 0, partition_bytes: int = 128):
+    """Candidate indices j_b and draws u_b of particle i, b = 0..B-1."""
+    j = np.zeros(max(B, 1), dtype=np.uint32)
+    u = np.zeros(max(B, 1), dtype=np.float32)
+    scratch = np.zeros(max(B, 1), dtype=np.uint32)
+    rc = lib().mgp_oracle_trace(n, _variant(variant), B, seed, stream_id, partition_bytes,
+                                _ptr(scratch, _u32p), i, _ptr(j, _u32p), _ptr(u, _f32p))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_trace")
+    return j[:B].astype(np.int64), u[:B]
+
+
+def gather(states: np.ndarray, anc: np.ndarray) -> np.ndarray:
+    states = np.ascontiguousarray(states, dtype=np.float32)
+    if states.ndim == 1:
+        states = states.reshape(-1, 1)
+    anc = np.ascontiguousarray(anc, dtype=np.int32)
+    n_states, d = states.shape
+    out = np.empty((anc.size, d), dtype=np.float32)
+    rc = lib().mgp_oracle_gather(_ptr(states, _f32p), n_states, d, _ptr(anc, _i32p), anc.size,
+                                 _ptr(out, _f32p))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_gather")
+    return out

@@ -1,0 +1,353 @@
+/*
+ * mgp_oracle.c -- plain, single-threaded CPU reference for Metropolis-family
+ * parallel resampling (Metropolis, Metropolis-C1, Metropolis-C2, Megopolis),
+ * after "The Megopolis Resampler: Memory Coalesced Resampling on GPUs"
+ * (Chesser, Nguyen, Ranasinghe; arXiv 2109.13504).
+ *
+ * TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load or call this library. The HIP
+ * product library never links, loads or calls it, and the two share no code,
+ * headers, tables or helpers. Build it with
+ *     gcc -std=c11 -O2 -ffp-contract=off -fno-fast-math -fPIC -shared -lm
+ * so that every fp32 product is one IEEE round-to-nearest-even multiply
+ * (x86-64 SSE, FLT_EVAL_METHOD == 0, denormals kept).
+ *
+ * What it computes, and where the paper defines it:
+ *   - Metropolis resample            : Algorithm 2 (Section 3)
+ *   - Metropolis-C1 / -C2 resample   : Algorithms 3 and 4 (Section 3.1)
+ *   - Megopolis resample             : Algorithm 5 (Section 4)
+ *   - number of iterations B         : eq. (bcalc) in Section 3 and
+ *                                      eq. (proposition), Section 4.1
+ *   - particle copy x_bar_i = x_k    : last statement of Algorithms 2-5
+ *
+ * The paper fixes the algorithms but not the random-number generator (it used
+ * a stateful generator on its GPU). Here every random draw is a pure function
+ * of (seed, stream, index, iteration) through the counter-based generator
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11), so each particle's chain can be recomputed alone.
+ * Stream layout (the HIP library implements the same layout independently):
+ *
+ *   key     = (low 32 bits of seed, high 32 bits of seed)
+ *   counter = (block, tag, stream_id, index)
+ *
+ *   tag 0  u draws        index = particle i, block = b / 5, five u per call
+ *   tag 1  j draws        index = particle i, block = b / 4, word b % 4
+ *   tag 2  Megopolis o_b  index = 0,          block = b / 4, word b % 4
+ *   tag 3  C1 partition   index = group g,    block = 0,     word 0
+ *   tag 4  C2 partition   index = group g,    block = b / 4, word b % 4
+ *
+ * with group g = floor(i / 32) (the paper's warp index). Maps from 32-bit words:
+ *   u in (0,1]   : m = 24 random bits, u = (m + 1) * 2^-24   (exact in fp32)
+ *                  call words x0..x3 give m = x_r >> 8 for r < 4 and
+ *                  m = (x0 & 255) | (x1 & 255) << 8 | (x2 & 255) << 16 for r = 4
+ *   U{0, n-1}    : floor(x * n / 2^32)
+ *
+ * Every function is a transcription of the paper's definition in the paper's
+ * order, with no blocking, fusion or reordering.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#define OR_METROPOLIS 0
+#define OR_C1 1
+#define OR_C2 2
+#define OR_MEGOPOLIS 3
+
+#define OR_TAG_U 0u
+#define OR_TAG_J 1u
+#define OR_TAG_OFFSET 2u
+#define OR_TAG_C1_PART 3u
+#define OR_TAG_C2_PART 4u
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ERANGE (-2)
+#define OR_EWEIGHTS (-6)
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11): ten rounds of the Philox S-box on a  */
+/* 4 x 32-bit counter; the 2 x 32-bit key is advanced by the Weyl constants   */
+/* between rounds.                                                            */
+/* ------------------------------------------------------------------------ */
+void mgp_oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+static void draw_words(uint64_t seed, uint32_t tag, uint32_t stream_id, uint32_t index,
+                       uint32_t block, uint32_t x[4])
+{
+    uint32_t ctr[4] = {block, tag, stream_id, index};
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    mgp_oracle_philox4x32_10(ctr, key, x);
+}
+
+/* U{0, n-1} from one 32-bit word. */
+static uint32_t uniform_index(uint32_t x, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)x * (uint64_t)n) >> 32);
+}
+
+/* u ~ U(0,1] for particle i at iteration b (the "u ~ U[0,1]" draw of
+ * Algorithms 2-5). */
+float mgp_oracle_draw_u(uint64_t seed, uint32_t stream_id, uint32_t i, uint32_t b)
+{
+    uint32_t x[4];
+    draw_words(seed, OR_TAG_U, stream_id, i, b / 5u, x);
+    uint32_t r = b % 5u;
+    uint32_t m;
+    if (r < 4u)
+        m = x[r] >> 8;
+    else
+        m = (x[0] & 0xFFu) | ((x[1] & 0xFFu) << 8) | ((x[2] & 0xFFu) << 16);
+    float mf = (float)(m + 1u); /* <= 2^24, exact */
+    return mf * 0x1p-24f;       /* power-of-two scaling, exact */
+}
+
+/* The b-th Megopolis offset o_b ~ U{0, N-1}, shared by every particle
+ * (Algorithm 5, offsets drawn as a separate task before the particle loop). */
+uint32_t mgp_oracle_offset(uint64_t seed, uint32_t stream_id, uint32_t n, uint32_t b)
+{
+    uint32_t x[4];
+    draw_words(seed, OR_TAG_OFFSET, stream_id, 0u, b / 4u, x);
+    return uniform_index(x[b % 4u], n);
+}
+
+void mgp_oracle_offsets(uint64_t seed, uint32_t stream_id, uint32_t n, uint32_t B, uint32_t* o)
+{
+    for (uint32_t b = 0; b < B; ++b)
+        o[b] = mgp_oracle_offset(seed, stream_id, n, b);
+}
+
+/* Megopolis candidate index (Algorithm 5): aligned particle index, plus the
+ * aligned part of the offset, plus the offset inside the 32-wide segment,
+ * all taken mod N. */
+uint32_t mgp_oracle_megopolis_index(uint32_t i, uint32_t o, uint32_t n)
+{
+    uint64_t i_aligned = (uint64_t)i - (uint64_t)(i % 32u);
+    uint64_t o_aligned = (uint64_t)o - (uint64_t)(o % 32u);
+    uint64_t o_unaligned = ((uint64_t)i + (uint64_t)o) % 32u;
+    return (uint32_t)((i_aligned + o_aligned + o_unaligned) % (uint64_t)n);
+}
+
+/* Metropolis-C1/C2 candidate index (Algorithms 3 and 4): a partition p of
+ * N_w = P_size / 4 weights, then j uniform inside it. The paper's
+ * N_part = 4N / P_size is read as ceil(N / N_w) and the last partition is cut
+ * at N, so that every index is valid for any N. */
+static uint32_t partition_index(uint32_t n, uint32_t n_w, uint32_t part_word, uint32_t j_word)
+{
+    uint32_t n_part = (uint32_t)(((uint64_t)n + n_w - 1u) / n_w);
+    uint32_t p = uniform_index(part_word, n_part);
+    uint64_t start = (uint64_t)p * n_w;
+    uint64_t width = (uint64_t)n - start;
+    if (width > n_w) width = n_w;
+    return (uint32_t)(start + uniform_index(j_word, (uint32_t)width));
+}
+
+/* Candidate index j for particle i at iteration b, for each variant.
+ * `offsets` holds o_0..o_{B-1} (Megopolis only). */
+static uint32_t proposal(int variant, uint32_t n, uint32_t n_w, uint64_t seed, uint32_t stream_id,
+                         const uint32_t* offsets, uint32_t i, uint32_t b)
+{
+    uint32_t x[4], px[4];
+    switch (variant) {
+    case OR_METROPOLIS: /* j ~ U{0, N-1} (Algorithm 2) */
+        draw_words(seed, OR_TAG_J, stream_id, i, b / 4u, x);
+        return uniform_index(x[b % 4u], n);
+    case OR_C1: /* one partition per group for all b (Algorithm 3) */
+        draw_words(seed, OR_TAG_C1_PART, stream_id, i / 32u, 0u, px);
+        draw_words(seed, OR_TAG_J, stream_id, i, b / 4u, x);
+        return partition_index(n, n_w, px[0], x[b % 4u]);
+    case OR_C2: /* a new partition per group at every b (Algorithm 4) */
+        draw_words(seed, OR_TAG_C2_PART, stream_id, i / 32u, b / 4u, px);
+        draw_words(seed, OR_TAG_J, stream_id, i, b / 4u, x);
+        return partition_index(n, n_w, px[b % 4u], x[b % 4u]);
+    default: /* OR_MEGOPOLIS */
+        return mgp_oracle_megopolis_index(i, offsets[b], n);
+    }
+}
+
+static int check_common(int variant, int32_t n, uint32_t partition_bytes)
+{
+    if (n < 1) return OR_EINVAL;
+    if (variant < OR_METROPOLIS || variant > OR_MEGOPOLIS) return OR_EINVAL;
+    if ((variant == OR_C1 || variant == OR_C2) &&
+        (partition_bytes < 4u || partition_bytes % 4u != 0u))
+        return OR_EINVAL;
+    return OR_OK;
+}
+
+/* One particle's chain: k <- i, then B accept/reject steps against candidate
+ * j with the ratio test u <= w_j / w_k written as the fp32 product
+ * u * w_k <= w_j (ties accept). Returns the ancestor k. */
+static int32_t run_chain(const float* w, uint32_t n, int variant, uint32_t B, uint64_t seed,
+                         uint32_t stream_id, uint32_t n_w, const uint32_t* offsets, uint32_t i,
+                         uint64_t* accepts)
+{
+    uint32_t k = i;
+    for (uint32_t b = 0; b < B; ++b) {
+        uint32_t j = proposal(variant, n, n_w, seed, stream_id, offsets, i, b);
+        float u = mgp_oracle_draw_u(seed, stream_id, i, b);
+        float p = u * w[k];
+        if (p <= w[j]) {
+            k = j;
+            if (accepts) *accepts += 1u;
+        }
+    }
+    return (int32_t)k;
+}
+
+/* Full resample: ancestors for all N particles. The offsets of a Megopolis
+ * call are generated first, then the particle loop runs. `offsets_scratch`
+ * must hold B entries (Megopolis only; may be NULL otherwise). */
+int mgp_oracle_resample(const float* w, int32_t n, int variant, uint32_t B, uint64_t seed,
+                        uint32_t stream_id, uint32_t partition_bytes, uint32_t* offsets_scratch,
+                        int32_t* ancestors, uint64_t* accepts)
+{
+    int rc = check_common(variant, n, partition_bytes);
+    if (rc) return rc;
+    if (variant == OR_MEGOPOLIS) {
+        if (!offsets_scratch) return OR_EINVAL;
+        mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
+    }
+    if (accepts) *accepts = 0;
+    uint32_t n_w = partition_bytes / 4u;
+    for (uint32_t i = 0; i < (uint32_t)n; ++i)
+        ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w,
+                                 offsets_scratch, i, accepts);
+    return OR_OK;
+}
+
+/* Ancestors for a subset of particles only (each chain is independent). */
+int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t B, uint64_t seed,
+                               uint32_t stream_id, uint32_t partition_bytes,
+                               uint32_t* offsets_scratch, const int32_t* idx, int32_t count,
+                               int32_t* ancestors)
+{
+    int rc = check_common(variant, n, partition_bytes);
+    if (rc) return rc;
+    if (variant == OR_MEGOPOLIS) {
+        if (!offsets_scratch) return OR_EINVAL;
+        mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
+    }
+    uint32_t n_w = partition_bytes / 4u;
+    for (int32_t c = 0; c < count; ++c) {
+        if (idx[c] < 0 || idx[c] >= n) return OR_EINVAL;
+        ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w,
+                                 offsets_scratch, (uint32_t)idx[c], NULL);
+    }
+    return OR_OK;
+}
+
+/* The candidate indices j_0..j_{B-1} and draws u_0..u_{B-1} of particle i
+ * (for tests that check the accept logic against the draws). */
+int mgp_oracle_trace(int32_t n, int variant, uint32_t B, uint64_t seed, uint32_t stream_id,
+                     uint32_t partition_bytes, uint32_t* offsets_scratch, int32_t i,
+                     uint32_t* j_out, float* u_out)
+{
+    int rc = check_common(variant, n, partition_bytes);
+    if (rc) return rc;
+    if (i < 0 || i >= n) return OR_EINVAL;
+    if (variant == OR_MEGOPOLIS) {
+        if (!offsets_scratch) return OR_EINVAL;
+        mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
+    }
+    uint32_t n_w = partition_bytes / 4u;
+    for (uint32_t b = 0; b < B; ++b) {
+        j_out[b] = proposal(variant, (uint32_t)n, n_w, seed, stream_id, offsets_scratch,
+                            (uint32_t)i, b);
+        u_out[b] = mgp_oracle_draw_u(seed, stream_id, (uint32_t)i, b);
+    }
+    return OR_OK;
+}
+
+/* Weight statistics needed by the B rule: max(w) in fp32 (exact, order-free),
+ * sum(w) accumulated in fp64 in index order. Weights must be finite, >= 0,
+ * and not all zero. */
+int mgp_oracle_reduce(const float* w, int32_t n, float* w_max, double* w_sum)
+{
+    if (n < 1) return OR_EINVAL;
+    float mx = 0.0f;
+    double s = 0.0;
+    int bad = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        float v = w[i];
+        if (!(v >= 0.0f) || isinf(v)) bad = 1;
+        if (v > mx) mx = v;
+        s += (double)v;
+    }
+    *w_max = mx;
+    *w_sum = s;
+    if (bad || !(mx > 0.0f)) return OR_EWEIGHTS;
+    return OR_OK;
+}
+
+/* Number of iterations, eq. (proposition):
+ *     B = ceil( log(eps) / log(1 - E(w) / max(w)) )
+ * with E(w) the sample mean, in fp64 (log1p for the denominator). If
+ * E(w) / max(w) >= 1 (all weights equal) one iteration suffices. The result
+ * is at least 1 and is clamped to b_max (reported through *clamped). */
+int mgp_oracle_choose_B(double w_sum, float w_max, int32_t n, double eps, uint32_t b_max,
+                        uint32_t* B, double* raw_out, int* clamped)
+{
+    if (n < 1 || !(eps > 0.0) || !(eps <= 1.0) || b_max < 1u) return OR_EINVAL;
+    double mean = w_sum / (double)n;
+    double r = mean / (double)w_max;
+    double raw;
+    *clamped = 0;
+    if (r >= 1.0) {
+        raw = 1.0;
+    } else {
+        raw = log(eps) / log1p(-r);
+    }
+    if (raw_out) *raw_out = raw;
+    double c = ceil(raw);
+    if (c < 1.0) c = 1.0;
+    if (c > (double)b_max) {
+        c = (double)b_max;
+        *clamped = 1;
+    }
+    *B = (uint32_t)c;
+    return OR_OK;
+}
+
+/* x_bar_i = x_{k_i}: copy the D-dimensional state row of each ancestor. */
+int mgp_oracle_gather(const float* states, int32_t n_states, int32_t d, const int32_t* ancestors,
+                      int32_t n_out, float* out)
+{
+    if (n_states < 1 || d < 1 || n_out < 0) return OR_EINVAL;
+    for (int32_t i = 0; i < n_out; ++i) {
+        int32_t k = ancestors[i];
+        if (k < 0 || k >= n_states) return OR_ERANGE;
+        for (int32_t c = 0; c < d; ++c)
+            out[(size_t)i * (size_t)d + (size_t)c] = states[(size_t)k * (size_t)d + (size_t)c];
+    }
+    return OR_OK;
+}

@@ -1,0 +1,39 @@
+"""Statistical pin of the whole oracle against the paper's own measurements:
+MSE/N at N = 32768 for Megopolis, Metropolis, C1 and C2 (Tables 3-6, first
+row), Gaussian-likelihood weights, eps = 0.01, B from eq. (proposition).
+
+The paper averages 16 weight sequences x 256 runs; this test uses 4
+sequences and fewer runs, and allows 4 standard errors of its own estimate
+plus 1% of the printed value."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.metrics import QualityAccumulator
+from paper_2109_13504_amd import inputs
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mse_over_n_N32768.json")))
+RUNS_PER_SEQ = {0: 6, 1: 6, 2: 4, 3: 2, 4: 1}
+CASES = [(row["variant"], row["partition_bytes"], y, row["mse_over_n"][y])
+         for row in GOLDEN["rows"] for y in range(5)]
+
+
+@pytest.mark.parametrize("variant,ps,y,expect", CASES,
+                         ids=[f"{v}-ps{ps}-y{y}" for v, ps, y, _ in CASES])
+def test_mse_over_n_matches_paper_tables(variant, ps, y, expect):
+    n = GOLDEN["n"]
+    per_run = []
+    for q in range(4):
+        w = inputs.gaussian_weights(n, y, q)
+        B, _, _ = oracle.B_from_weights(w, GOLDEN["eps"])
+        acc = QualityAccumulator(w)
+        for k in range(RUNS_PER_SEQ[y]):
+            acc.add(oracle.resample(w, variant, B, 100 * q + k + 1, partition_bytes=ps))
+        per_run += [se / n for se in acc.se_list]
+    per_run = np.array(per_run)
+    est = per_run.mean()
+    stderr = per_run.std(ddof=1) / np.sqrt(per_run.size)
+    assert abs(est - expect) <= 4 * stderr + 0.01 * expect, (est, expect, stderr)
