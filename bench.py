@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the resampling hot path on one MI355X.
+
+A step is one pass of the single-filter path over the N = 2^24 workload
+(Gaussian-likelihood weights, y = 4, eps = 0.01, so B ~ 353), through the
+HIP library's C ABI:
+    mgp_compute_B          reduction (fp32 max, fp64 sum), B, Megopolis offsets
+    mgp_resample_prepared  the accept loop (the dominant kernel)
+    mgp_gather             x_bar_i = x_{k_i}, D = 8 fp32 states
+Each step uses a new seed. The weights and states are resident in HBM
+before the timed region. Metropolis is timed the same way for comparison.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "particles resampled/s at N=2^24 (Megopolis vs Metropolis) + % HBM peak; p99"
+LOOP_SOURCES = ["paper_2109_13504_amd/csrc/mgp_device.h", "paper_2109_13504_amd/csrc/mgp_kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_megopolis_loop_n2pow24_y4.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in LOOP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", default="megopolis", choices=["megopolis", "metropolis", "c1", "c2"])
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--y", type=float, default=4.0)
+    ap.add_argument("--eps", type=float, default=0.01)
+    ap.add_argument("--d", type=int, default=8)
+    ap.add_argument("--metropolis-steps", type=int, default=3)
+    ap.add_argument("--no-metropolis", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=16, help="oracle runs every k-th particle's chain")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
+    return ap.parse_args()
+
+
+def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup, seed0):
+    """Runs warmup + steps; returns wall ms per step and per-step event times."""
+    stream = torch.cuda.current_stream()
+    n = w.numel()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+
+    def one(s, e):
+        seed = seed0 + s
+        if e:
+            e[0].record(stream)
+        r.compute_B(w, variant, epsilon=eps, seed=seed)
+        if e:
+            e[1].record(stream)
+        r.resample_prepared(w, variant, epsilon=eps, seed=seed, out=anc)
+        if e:
+            e[2].record(stream)
+        mgp.gather(states, anc, out=out)
+        if e:
+            e[3].record(stream)
+
+    for s in range(warmup):
+        one(1000 + s, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        one(s, ev[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {"total": [], "reduce_B": [], "loop": [], "gather": []}
+    for e in ev:
+        per["reduce_B"].append(e[0].elapsed_time(e[1]))
+        per["loop"].append(e[1].elapsed_time(e[2]))
+        per["gather"].append(e[2].elapsed_time(e[3]))
+        per["total"].append(e[0].elapsed_time(e[3]))
+    return (t1 - t0) * 1000.0 / steps, per
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def cpu_baseline(w_np, variant, eps, stride):
+    """The oracle as it is, single-threaded, on a bounded sample: the full
+    reduction and B, then the chains of every stride-th particle."""
+    import numpy as np
+
+    import oracle
+    n = w_np.size
+    idx = np.arange(0, n, stride, dtype=np.int32)
+    t0 = time.perf_counter()
+    B, _, _ = oracle.B_from_weights(w_np, eps)
+    oracle.resample_subset(w_np, variant, B, 12345, idx)
+    dt = time.perf_counter() - t0
+    return {"value": idx.size / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"single-threaded C oracle: fp64 reduction + B over all {n} weights, then the B-step chains "
+                      f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2109_13504_amd import inputs, mgp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mgp.lib()
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    log(f"[bench] generating inputs N=2^{args.log2n} y={args.y} D={args.d}")
+    w_np, st_np = inputs.gaussian_weights_and_states(n, args.y, args.d, 0)
+    w = torch.from_numpy(w_np).to(dev)
+    states = torch.from_numpy(st_np).to(dev)
+    del st_np
+    anc = torch.empty(n, dtype=torch.int32, device=dev)
+    out = torch.empty((n, args.d), dtype=torch.float32, device=dev)
+    r = mgp.Resampler(n)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    log(f"[bench] {args.variant}: warmup {args.warmup}, steps {args.steps}")
+    ms, per = timed_steps(torch, mgp, r, w, states, anc, out, args.variant, args.eps, args.steps, args.warmup, 0)
+    st = r.last_stats()
+    B = st["B"]
+    assert st["status"] == 0
+    loop_ms = float(np.mean(per["loop"]))
+    loop_bytes = 4.0 * n * (B + 2)  # B candidate weights + own weight + ancestor write, per particle
+    achieved = loop_bytes / (loop_ms * 1e-3) / 1e9
+    step_bytes = 4.0 * n + 4.0 * n * (B + 2) + 4.0 * n * (2 * args.d + 1)
+    log(f"[bench] {args.variant}: {ms:.3f} ms/step, loop {loop_ms:.3f} ms, B={B}, {achieved:.0f} GB/s effective")
+
+    result = {
+        "metric": METRIC,
+        "value": n / (ms * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"single filter, N=2^{args.log2n}, Gaussian-likelihood weights y={args.y:g}, "
+                               f"eps={args.eps:g} (B={B}), {args.variant}, gather of D={args.d} fp32 states",
+                   "n": n, "y": args.y, "eps": args.eps, "B": B, "d": args.d, "variant": args.variant,
+                   "step": "compute_B + accept loop + gather"},
+        "p50_ms": pct(per["total"], 50),
+        "p99_ms": pct(per["total"], 99),
+        "phase_ms": {k: float(np.mean(v)) for k, v in per.items()},
+        "hbm_frac_effective": (step_bytes / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
+        "roofline": {
+            "kernel": f"k_resample<{args.variant}> (accept loop)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": loop_bytes,
+            "avg_launch_ms": loop_ms,
+            "traffic": None,
+        },
+    }
+
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("source_hash") == source_hash() and t.get("n") == n and t.get("B") == B:
+            result["roofline"]["traffic"] = t["hbm_bytes_per_launch"]
+
+    if not args.no_metropolis and args.variant != "metropolis":
+        log(f"[bench] metropolis: {args.metropolis_steps} steps")
+        ms_m, per_m = timed_steps(torch, mgp, r, w, states, anc, out, "metropolis", args.eps,
+                                  args.metropolis_steps, 1, 0)
+        lm = float(np.mean(per_m["loop"]))
+        result["metropolis"] = {"value": n / (ms_m * 1e-3), "unit": "particles/s", "ms_per_step": ms_m,
+                                "loop_ms": lm, "effective_GBs": loop_bytes / (lm * 1e-3) / 1e9,
+                                "p99_ms": pct(per_m["total"], 99)}
+        result["speedup_vs_metropolis"] = ms_m / ms
+        log(f"[bench] metropolis: {ms_m:.3f} ms/step, loop {lm:.3f} ms -> speedup {ms_m / ms:.2f}x")
+
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(w_np, args.variant, args.eps, args.cpu_stride)
+        log(f"[bench] cpu baseline: {result['cpu_baseline']['value']:.3e} particles/s")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

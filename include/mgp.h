@@ -1,0 +1,136 @@
+/*
+ * mgp.h -- C ABI of libmgp, Metropolis-family parallel resampling on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is that of "The Megopolis Resampler: Memory Coalesced Resampling
+ * on GPUs" (Chesser, Nguyen, Ranasinghe; arXiv 2109.13504): every particle i
+ * runs B accept/reject steps against candidate ancestors and the output is
+ * one ancestor index per particle (Section 3: "a list containing an ancestor
+ * for each particle"). Weights need not be normalised (Section 7 removes the
+ * normalisation stage for exactly this reason).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device pointers (HBM of the current device);
+ *     everything else is host memory. The caller owns every buffer it passes;
+ *     the library allocates only inside batch-plan and server objects and
+ *     frees that memory when the object is destroyed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream, like HIP's own: a return of
+ *     MGP_OK means the work was enqueued.
+ *   - Argument errors are reported synchronously with a negative MGP_E* code
+ *     and a thread-local message (mgp_last_error). Nothing is enqueued then.
+ *   - Data errors found on the device (a weight that is NaN, infinite or
+ *     negative, or all weights zero) are reported in mgp_stats.status as
+ *     MGP_EWEIGHTS; every ancestor is then written as -1.
+ *   - Results are pure functions of (weights, variant, B, seed, stream_id,
+ *     partition_bytes): identical across calls, launch shapes and batches.
+ */
+#ifndef MGP_H
+#define MGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define MGP_OK 0
+#define MGP_EINVAL (-1)   /* bad argument (null pointer, n < 1, bad variant, eps out of range, ...) */
+#define MGP_ERANGE (-2)   /* B above b_max, workspace too small, size out of range */
+#define MGP_ENOMEM (-3)   /* device memory or HBM budget exhausted */
+#define MGP_EHIP (-4)     /* a HIP runtime call or kernel launch failed */
+#define MGP_EBUSY (-5)    /* object in use / request not finished */
+#define MGP_EWEIGHTS (-6) /* device-side status: invalid weights */
+
+/* ---- resamplers --------------------------------------------------------- */
+typedef enum mgp_variant {
+    MGP_METROPOLIS = 0, /* Algorithm 2: j ~ U{0, N-1} per particle and step */
+    MGP_C1 = 1,         /* Algorithm 3: one partition per 32-particle group for all steps */
+    MGP_C2 = 2,         /* Algorithm 4: a new partition per group at every step */
+    MGP_MEGOPOLIS = 3   /* Algorithm 5: B offsets shared by every particle, wrapped 32-segments */
+} mgp_variant;
+
+typedef struct mgp_params {
+    int32_t variant;          /* mgp_variant */
+    uint32_t B;               /* > 0: run exactly B steps; 0: derive B from epsilon */
+    double epsilon;           /* bias bound in (0, 1] of eq. (proposition); used when B == 0 */
+    uint64_t seed;            /* Philox4x32-10 key */
+    uint32_t stream_id;       /* Philox counter word 2: 0 for a single filter, filter / request id otherwise */
+    uint32_t partition_bytes; /* C1/C2 partition size P_size in bytes, multiple of 4; 0 means 128 */
+    uint32_t b_max;           /* upper clamp for a derived B, and the limit for an explicit B; 0 means 65536 */
+    uint32_t reserved;        /* must be 0 */
+} mgp_params;
+
+/* Written on the device by mgp_resample / mgp_compute_B (48 bytes). */
+typedef struct mgp_stats {
+    double w_sum;     /* sum of the weights, fp64 */
+    double ratio;     /* E(w) / max(w), fp64 */
+    double b_raw;     /* log(eps) / log(1 - ratio) before ceil / clamp; 0 when B was given */
+    float w_max;      /* max(w), fp32 */
+    uint32_t B;       /* iterations used (0 when status != MGP_OK) */
+    uint32_t clamped; /* 1 if the derived B was clamped to b_max */
+    int32_t status;   /* MGP_OK or MGP_EWEIGHTS */
+    uint32_t n;       /* number of particles */
+    uint32_t tag;     /* hash of (n, variant, seed, stream_id) of the call that wrote it */
+} mgp_stats;
+
+/* Bytes of device workspace mgp_resample / mgp_compute_B need for n
+ * particles with these params (it grows with b_max, for the Megopolis
+ * offsets). Host-only; touches no device. */
+int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes);
+
+/* RESAMPLE(x, w) -> ancestors (Algorithms 2-5; Section 3 for the problem
+ * statement). Steps, all on `stream`:
+ *   1. reduce the weights: fp32 max, fp64 sum, validation;
+ *   2. B = params->B, or ceil(log eps / log(1 - E(w)/max w)) from eq.
+ *      (proposition) (Section 4.1), clamped to [1, b_max]; Megopolis offsets
+ *      o_0..o_{B-1} (Algorithm 5) are generated here;
+ *   3. the accept loop: ancestors_dev[i] = k_i for i in [0, n).
+ * w_dev          : n fp32 weights, device, contiguous, >= 0 and finite.
+ * ancestors_dev  : n int32, device, written.
+ * stats_dev      : device mgp_stats written by step 2, or NULL.
+ * workspace_dev  : >= mgp_workspace_size bytes of device memory, 256-byte
+ *                  aligned, owned by the caller; no initialisation needed. Its
+ *                  contents are scratch between calls; calls that share a
+ *                  workspace must be ordered (same stream or synchronised). */
+int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
+                 mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Steps 1 and 2 of mgp_resample only: the reduction, B, and (for
+ * MGP_MEGOPOLIS) the offsets, kept in the workspace for a following
+ * mgp_resample_prepared. The paper leaves B to be pre-estimated when its
+ * cost matters (Section 3); this split lets a caller time or reuse it.
+ * stats_dev: device mgp_stats, written (may be NULL). */
+int mgp_compute_B(const float* w_dev, int32_t n, const mgp_params* params, mgp_stats* stats_dev,
+                  void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Step 3 of mgp_resample only: the accept loop, using the B, status and
+ * offsets that the preceding mgp_compute_B on this workspace left there.
+ * params and n must equal that call's; the kernel checks a tag of
+ * (n, variant, seed, stream_id) written by mgp_compute_B, and on a mismatch
+ * (or invalid weights) writes -1 to every ancestor. */
+int mgp_resample_prepared(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
+                          void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Particle copy x_bar_i = x_{k_i} (last statement of Algorithms 2-5):
+ * out_dev[i][c] = states_dev[ancestors_dev[i]][c] for i < n_out, c < d.
+ * states_dev : n_states x d fp32, row-major (array of structures), device.
+ * out_dev    : n_out x d fp32, device, written; must not overlap states_dev.
+ * An ancestor outside [0, n_states) (e.g. the -1 of a failed resample)
+ * yields a row of NaN, never an out-of-bounds read. */
+int mgp_gather(const float* states_dev, int32_t n_states, int32_t d, const int32_t* ancestors_dev,
+               int32_t n_out, float* out_dev, void* stream);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* mgp_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int mgp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGP_H */

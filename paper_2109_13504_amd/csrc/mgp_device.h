@@ -1,0 +1,257 @@
+// mgp_device.h -- device-side building blocks of the resampling kernels for
+// gfx950: the counter-based generator, the u and index maps, the candidate
+// index of each variant, and the accept loop of one particle.
+//
+// Definitions (Algorithms 2-5 of "The Megopolis Resampler", arXiv 2109.13504):
+//   - particle i starts at k = i and runs B steps; at step b a candidate j is
+//     drawn and accepted when u * w_k <= w_j (the ratio test u <= w_j / w_k in
+//     product form, evaluated in fp32, ties accept);
+//   - Metropolis: j ~ U{0, N-1}; C1: j uniform in the partition the particle's
+//     32-group drew once; C2: the group redraws its partition every step;
+//     Megopolis: j = (i - i mod 32 + o_b - o_b mod 32 + (i + o_b) mod 32) mod N
+//     with offsets o_b shared by every particle.
+// Random streams: Philox4x32-10 (Salmon et al., SC'11), key = seed,
+// counter = (block, tag, stream_id, index). The per-particle index sits in the
+// last counter word so that the first round is wave-uniform (scalar unit)
+// and rounds 2 and 3 carry one uniform multiply each.
+//   tag 0: u, index i, block b/5, five u per call
+//   tag 1: j, index i, block b/4, word b%4
+//   tag 2: Megopolis offsets, index 0, block b/4, word b%4
+//   tag 3: C1 partition, index i/32, block 0, word 0
+//   tag 4: C2 partition, index i/32, block b/4, word b%4
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgp {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kWeyl0 = 0x9E3779B9u;
+constexpr uint32_t kWeyl1 = 0xBB67AE85u;
+
+constexpr uint32_t kTagU = 0u;
+constexpr uint32_t kTagJ = 1u;
+constexpr uint32_t kTagOffset = 2u;
+constexpr uint32_t kTagC1Part = 3u;
+constexpr uint32_t kTagC2Part = 4u;
+
+constexpr int kMetropolis = 0;
+constexpr int kC1 = 1;
+constexpr int kC2 = 2;
+constexpr int kMegopolis = 3;
+
+constexpr uint32_t kSegment = 32u;  // weights per wrapped segment (the paper's warp width)
+
+struct Words {
+    uint32_t x0, x1, x2, x3;
+};
+
+// Philox4x32-10 on counter (c0, c1, c2, c3) with key (k0, k1).
+__device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(kPhiloxM0, c0);
+        const uint32_t lo0 = kPhiloxM0 * c0;
+        const uint32_t hi1 = __umulhi(kPhiloxM1, c2);
+        const uint32_t lo1 = kPhiloxM1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+    return Words{c0, c1, c2, c3};
+}
+
+// U{0, n-1} from a 32-bit word: floor(x * n / 2^32).
+__device__ __forceinline__ uint32_t uniform_index(uint32_t x, uint32_t n) { return __umulhi(x, n); }
+
+// u = (m + 1) 2^-24 for a 24-bit m; m 2^-24 + 2^-24 is exact, so the fused
+// multiply-add rounds nothing.
+__device__ __forceinline__ float u_from_bits(uint32_t m) { return __fmaf_rn((float)m, 0x1p-24f, 0x1p-24f); }
+
+// The five u of one tag-0 call.
+struct UBlock {
+    float u[5];
+};
+
+__device__ __forceinline__ UBlock u_block(const Words& x)
+{
+    UBlock r;
+    r.u[0] = u_from_bits(x.x0 >> 8);
+    r.u[1] = u_from_bits(x.x1 >> 8);
+    r.u[2] = u_from_bits(x.x2 >> 8);
+    r.u[3] = u_from_bits(x.x3 >> 8);
+    r.u[4] = u_from_bits((x.x0 & 0xFFu) | ((x.x1 & 0xFFu) << 8) | ((x.x2 & 0xFFu) << 16));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t word(const Words& x, uint32_t r)
+{
+    return r == 0 ? x.x0 : r == 1 ? x.x1 : r == 2 ? x.x2 : x.x3;
+}
+
+// Megopolis candidate: aligned segment of i plus aligned part of o, rotated by
+// (i + o) mod 32 inside the segment; the sum is <= i + o <= 2N - 2, so one
+// conditional subtraction is the mod N. min(j, j - n) in unsigned arithmetic
+// picks j - n exactly when j >= n (n <= 2^31).
+__device__ __forceinline__ uint32_t megopolis_index(uint32_t i_aligned, uint32_t i_low, uint32_t o, uint32_t n)
+{
+    const uint32_t j = i_aligned + (o & ~(kSegment - 1u)) + ((i_low + o) & (kSegment - 1u));
+    const uint32_t jm = j - n;
+    return jm < j ? jm : j;
+}
+
+// C1/C2 candidate inside partition p of n_w weights (the last one cut at n).
+__device__ __forceinline__ uint32_t partition_index(uint32_t p, uint32_t jword, uint32_t n, uint32_t n_w)
+{
+    const uint32_t start = p * n_w;
+    const uint32_t rest = n - start;
+    const uint32_t width = rest < n_w ? rest : n_w;
+    return start + uniform_index(jword, width);
+}
+
+// Loads w[j]. With `Narrow` the byte offset fits 32 bits (n <= 2^30), which
+// lets the compiler use the scalar-base + 32-bit vector-offset form.
+template <bool Narrow>
+__device__ __forceinline__ float load_weight(const float* __restrict__ w, uint32_t j)
+{
+    if constexpr (Narrow) {
+        return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(w) + (j << 2));
+    } else {
+        return w[(size_t)j];
+    }
+}
+
+// Per-call parameters of the accept loop (all wave-uniform).
+struct LoopParams {
+    const float* w;
+    const uint32_t* offsets;  // Megopolis offsets o_0..o_{B-1}, each < n
+    uint32_t n;
+    uint32_t B;
+    uint32_t key0, key1;
+    uint32_t stream_id;
+    uint32_t n_w;     // C1/C2: weights per partition
+    uint32_t n_part;  // C1/C2: number of partitions, ceil(n / n_w)
+};
+
+// o_b, clamped below n so that a workspace not written by this call's
+// reduction can never steer a load out of bounds (wave-uniform, scalar unit).
+__device__ __forceinline__ uint32_t offset_at(const LoopParams& P, uint32_t b)
+{
+    const uint32_t o = P.offsets[b];
+    return o < P.n ? o : P.n - 1u;
+}
+
+// Steps per unrolled block: Megopolis needs only the 5-step u blocks; the
+// others also use 4-step j blocks, so they unroll over lcm(4, 5) = 20.
+template <int V>
+struct Unroll {
+    static constexpr uint32_t value = (V == kMegopolis) ? 5u : 20u;
+};
+
+// The B-step chain of particle i; returns its ancestor.
+template <int V, bool Narrow>
+__device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
+{
+    const float* __restrict__ w = P.w;
+    uint32_t k = i;
+    float wk = load_weight<Narrow>(w, i);
+    const uint32_t i_aligned = i & ~(kSegment - 1u);
+    const uint32_t i_low = i & (kSegment - 1u);
+    const uint32_t group = i / kSegment;
+
+    uint32_t c1_part = 0;
+    if constexpr (V == kC1) {
+        const Words px = philox(0u, kTagC1Part, P.stream_id, group, P.key0, P.key1);
+        c1_part = uniform_index(px.x0, P.n_part);
+    }
+
+    constexpr uint32_t U = Unroll<V>::value;
+    const uint32_t nblk = P.B / U;
+    for (uint32_t q = 0; q < nblk; ++q) {
+        UBlock ub;
+        Words jb{}, pb{};
+        uint32_t jj[U];
+        float wj[U];
+        // candidates and their weights first: they do not depend on k
+#pragma unroll
+        for (uint32_t s = 0; s < U; ++s) {
+            const uint32_t b = q * U + s;
+            uint32_t j;
+            if constexpr (V == kMegopolis) {
+                j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n);
+            } else {
+                if (s % 4 == 0) {
+                    const uint32_t blk = q * (U / 4) + s / 4;
+                    jb = philox(blk, kTagJ, P.stream_id, i, P.key0, P.key1);
+                    if constexpr (V == kC2) pb = philox(blk, kTagC2Part, P.stream_id, group, P.key0, P.key1);
+                }
+                const uint32_t jw = word(jb, s % 4);
+                if constexpr (V == kMetropolis) {
+                    j = uniform_index(jw, P.n);
+                } else if constexpr (V == kC1) {
+                    j = partition_index(c1_part, jw, P.n, P.n_w);
+                } else {
+                    j = partition_index(uniform_index(word(pb, s % 4), P.n_part), jw, P.n, P.n_w);
+                }
+            }
+            jj[s] = j;
+            wj[s] = load_weight<Narrow>(w, j);
+        }
+        // then the serial accept chain
+#pragma unroll
+        for (uint32_t s = 0; s < U; ++s) {
+            if (s % 5 == 0) ub = u_block(philox(q * (U / 5) + s / 5, kTagU, P.stream_id, i, P.key0, P.key1));
+            const float p = ub.u[s % 5] * wk;
+            const bool acc = p <= wj[s];
+            k = acc ? jj[s] : k;
+            wk = acc ? wj[s] : wk;
+        }
+    }
+
+    // remaining B mod U steps, one at a time; a generator block is refreshed
+    // when a step starts a new one (the first tail step is a multiple of 20,
+    // or of 5 for Megopolis, which draws no j)
+    UBlock ub{};
+    Words jb{}, pb{};
+    for (uint32_t b = nblk * U; b < P.B; ++b) {
+        const uint32_t r5 = b % 5u;
+        const uint32_t r4 = b % 4u;
+        if (r5 == 0u) ub = u_block(philox(b / 5u, kTagU, P.stream_id, i, P.key0, P.key1));
+        uint32_t j;
+        if constexpr (V == kMegopolis) {
+            j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n);
+        } else {
+            if (r4 == 0u) {
+                jb = philox(b / 4u, kTagJ, P.stream_id, i, P.key0, P.key1);
+                if constexpr (V == kC2) pb = philox(b / 4u, kTagC2Part, P.stream_id, group, P.key0, P.key1);
+            }
+            const uint32_t jw = word(jb, r4);
+            if constexpr (V == kMetropolis) {
+                j = uniform_index(jw, P.n);
+            } else if constexpr (V == kC1) {
+                j = partition_index(c1_part, jw, P.n, P.n_w);
+            } else {
+                j = partition_index(uniform_index(word(pb, r4), P.n_part), jw, P.n, P.n_w);
+            }
+        }
+        const float wjv = load_weight<Narrow>(w, j);
+        const float u = r5 == 0 ? ub.u[0] : r5 == 1 ? ub.u[1] : r5 == 2 ? ub.u[2] : r5 == 3 ? ub.u[3] : ub.u[4];
+        const float p = u * wk;
+        if (p <= wjv) {
+            k = j;
+            wk = wjv;
+        }
+    }
+    return k;
+}
+
+}  // namespace mgp

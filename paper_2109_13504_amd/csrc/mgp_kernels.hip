@@ -1,0 +1,498 @@
+// mgp_kernels.hip -- single-filter kernels for gfx950 and the C ABI of
+// include/mgp.h: weight reduction, B selection and Megopolis offsets, the
+// four accept loops, and the particle gather.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "mgp.h"
+#include "mgp_device.h"
+#include "mgp_internal.h"
+
+namespace mgp {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512];
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MGP_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return MGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 1. Reduction: fp32 max, fp64 sum, invalid-weight flag, per block.
+//    The block decomposition depends on n only, so the fp64 sum (and B) is
+//    the same on every call.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fold(float v, float& mx, double& s, uint32_t& bad)
+{
+    bad |= (!(v >= 0.0f) || v == INFINITY) ? 1u : 0u;
+    mx = fmaxf(mx, v);
+    s += (double)v;
+}
+
+// Block-wide reduction of (max, sum, bad); result valid in thread 0.
+__device__ void block_reduce(float& mx, double& s, uint32_t& bad)
+{
+    __shared__ float smx[kReduceThreads / 64];
+    __shared__ double ssum[kReduceThreads / 64];
+    __shared__ uint32_t sbad[kReduceThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        s += __shfl_xor(s, off, 64);
+        bad |= __shfl_xor(bad, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        smx[wv] = mx;
+        ssum[wv] = s;
+        sbad[wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mx = smx[0];
+        s = ssum[0];
+        bad = sbad[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            mx = fmaxf(mx, smx[k]);
+            s += ssum[k];
+            bad |= sbad[k];
+        }
+    }
+}
+
+// Block b reduces w[b*chunk, min(n, (b+1)*chunk)); chunk is a multiple of 4
+// and, with Vec, w is 16-byte aligned so float4 loads stay aligned.
+template <bool Vec>
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* __restrict__ w, uint32_t n,
+                                                           uint32_t chunk, Partial* __restrict__ part)
+{
+    // trailing blocks may start at or past n when chunk was rounded up: their
+    // range is empty and they contribute the neutral partial
+    const uint64_t start = (uint64_t)blockIdx.x * chunk;
+    const uint64_t stop = start + chunk < (uint64_t)n ? start + chunk : (uint64_t)n;
+    const uint64_t end = stop > start ? stop : start;
+    float mx = 0.0f;
+    double s = 0.0;
+    uint32_t bad = 0;
+    if constexpr (Vec) {
+        const uint64_t end4 = start + ((end - start) & ~(uint64_t)3);
+        for (uint64_t i = start + 4ull * threadIdx.x; i < end4; i += 4ull * blockDim.x) {
+            const float4 v = *reinterpret_cast<const float4*>(w + i);
+            fold(v.x, mx, s, bad);
+            fold(v.y, mx, s, bad);
+            fold(v.z, mx, s, bad);
+            fold(v.w, mx, s, bad);
+        }
+        for (uint64_t i = end4 + threadIdx.x; i < end; i += blockDim.x) fold(w[i], mx, s, bad);
+    } else {
+        for (uint64_t i = start + threadIdx.x; i < end; i += blockDim.x) fold(w[i], mx, s, bad);
+    }
+    block_reduce(mx, s, bad);
+    if (threadIdx.x == 0) part[blockIdx.x] = Partial{s, mx, bad};
+}
+
+// ---------------------------------------------------------------------------
+// 2. Finalize: combine the partials, pick B by eq. (proposition), write the
+//    stats, and generate the Megopolis offsets o_0..o_{B-1} (Algorithm 5's
+//    offsets are drawn before the particle loop; here in parallel, four per
+//    Philox call).
+// ---------------------------------------------------------------------------
+__device__ void finalize_one(const Partial* __restrict__ part, uint32_t nparts, const FinalizeArgs& a,
+                             mgp_stats* __restrict__ st, mgp_stats* __restrict__ st_user,
+                             uint32_t* __restrict__ offsets)
+{
+    __shared__ uint32_t sB;
+    float mx = 0.0f;
+    double s = 0.0;
+    uint32_t bad = 0;
+    for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
+        const Partial q = part[p];
+        mx = fmaxf(mx, q.w_max);
+        s += q.w_sum;
+        bad |= q.bad;
+    }
+    block_reduce(mx, s, bad);
+    if (threadIdx.x == 0) {
+        mgp_stats r;
+        r.w_sum = s;
+        r.w_max = mx;
+        r.n = a.n;
+        r.clamped = 0;
+        r.tag = a.tag;
+        r.ratio = 0.0;
+        r.b_raw = 0.0;
+        if (bad || !(mx > 0.0f)) {
+            r.status = MGP_EWEIGHTS;
+            r.B = 0;
+        } else {
+            r.status = MGP_OK;
+            const double mean = s / (double)a.n;
+            const double ratio = mean / (double)mx;
+            r.ratio = ratio;
+            if (a.B_user > 0) {
+                r.B = a.B_user;
+            } else {
+                const double raw = ratio >= 1.0 ? 1.0 : log(a.eps) / log1p(-ratio);
+                r.b_raw = raw;
+                double c = ceil(raw);
+                if (c < 1.0) c = 1.0;
+                if (c > (double)a.b_max) {
+                    c = (double)a.b_max;
+                    r.clamped = 1;
+                }
+                r.B = (uint32_t)c;
+            }
+        }
+        *st = r;
+        if (st_user) *st_user = r;
+        sB = r.B;
+    }
+    __syncthreads();
+    const uint32_t B = sB;
+    if (a.make_offsets && B > 0) {
+        const uint32_t calls = (B + 3u) / 4u;
+        for (uint32_t c = threadIdx.x; c < calls; c += blockDim.x) {
+            const Words x = philox(c, kTagOffset, a.stream_id, 0u, a.key0, a.key1);
+            const uint32_t o[4] = {x.x0, x.x1, x.x2, x.x3};
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+                const uint32_t b = 4u * c + r;
+                if (b < B) offsets[b] = uniform_index(o[r], a.n);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_finalize(const Partial* __restrict__ part, uint32_t nparts,
+                                                             FinalizeArgs a, mgp_stats* __restrict__ st,
+                                                             mgp_stats* __restrict__ st_user,
+                                                             uint32_t* __restrict__ offsets)
+{
+    finalize_one(part, nparts, a, st, st_user, offsets);
+}
+
+// ---------------------------------------------------------------------------
+// 3. The accept loop, one particle per thread.
+// ---------------------------------------------------------------------------
+template <int V, bool Narrow>
+__global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restrict__ w, uint32_t n,
+                                                           const mgp_stats* __restrict__ st,
+                                                           const uint32_t* __restrict__ offsets, uint32_t key0,
+                                                           uint32_t key1, uint32_t stream_id, uint32_t n_w,
+                                                           uint32_t n_part, uint32_t tag, uint32_t b_cap,
+                                                           int32_t* __restrict__ anc)
+{
+    const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
+    const uint32_t B = st->B;
+    // the stats must come from the reduction of this very call (same n,
+    // variant, seed and stream), and B must fit the workspace
+    const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    if (i >= n) return;
+    if (!ok) {
+        anc[i] = -1;
+        return;
+    }
+    LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part};
+    anc[i] = (int32_t)run_chain<V, Narrow>(P, i);
+}
+
+// ---------------------------------------------------------------------------
+// 4. Gather: out[i] = states[anc[i]] (rows of d fp32). With d % 4 == 0 and
+//    16-byte aligned rows every thread copies one float4; otherwise one
+//    float. Out-of-range ancestors give NaN rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather_vec4(const float4* __restrict__ states, uint32_t n_states,
+                                                     uint32_t d4, const int32_t* __restrict__ anc, uint64_t total,
+                                                     float4* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint64_t row = t / d4;
+        const uint32_t c = (uint32_t)(t - row * d4);
+        const int32_t k = anc[row];
+        float4 v;
+        if (k >= 0 && (uint32_t)k < n_states) {
+            v = states[(uint64_t)k * d4 + c];
+        } else {
+            v = make_float4(NAN, NAN, NAN, NAN);
+        }
+        out[t] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_scalar(const float* __restrict__ states, uint32_t n_states,
+                                                       uint32_t d, const int32_t* __restrict__ anc, uint64_t total,
+                                                       float* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint64_t row = t / d;
+        const uint32_t c = (uint32_t)(t - row * d);
+        const int32_t k = anc[row];
+        out[t] = (k >= 0 && (uint32_t)k < n_states) ? states[(uint64_t)k * d + c] : NAN;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+uint32_t reduce_blocks(uint32_t n)
+{
+    // about 2048 weights per block, at most kMaxPartials blocks
+    uint64_t g = ((uint64_t)n + 2047u) / 2048u;
+    if (g > kMaxPartials) g = kMaxPartials;
+    if (g < 1) g = 1;
+    return (uint32_t)g;
+}
+
+uint32_t reduce_chunk(uint32_t n, uint32_t blocks)
+{
+    uint64_t c = ((uint64_t)n + blocks - 1) / blocks;
+    c = (c + 3u) & ~(uint64_t)3u;
+    return (uint32_t)c;
+}
+
+int normalize_params(const mgp_params* in, Params* out)
+{
+    if (!in) return fail(MGP_EINVAL, "params is NULL");
+    if (in->variant < MGP_METROPOLIS || in->variant > MGP_MEGOPOLIS)
+        return fail(MGP_EINVAL, "unknown variant %d", in->variant);
+    out->variant = in->variant;
+    out->B = in->B;
+    out->eps = in->epsilon;
+    out->seed = in->seed;
+    out->stream_id = in->stream_id;
+    out->partition_bytes = in->partition_bytes ? in->partition_bytes : 128u;
+    out->b_max = in->b_max ? in->b_max : kDefaultBMax;
+    if (in->reserved != 0) return fail(MGP_EINVAL, "params.reserved must be 0");
+    if (out->partition_bytes < 4u || out->partition_bytes % 4u != 0u)
+        return fail(MGP_EINVAL, "partition_bytes must be a positive multiple of 4 (got %u)", out->partition_bytes);
+    if (out->b_max > kBMaxLimit) return fail(MGP_ERANGE, "b_max %u above the limit %u", out->b_max, kBMaxLimit);
+    if (out->B == 0) {
+        if (!(out->eps > 0.0) || !(out->eps <= 1.0))
+            return fail(MGP_EINVAL, "epsilon must be in (0, 1] when B is 0 (got %g)", out->eps);
+    } else if (out->B > out->b_max) {
+        return fail(MGP_ERANGE, "B = %u above b_max = %u", out->B, out->b_max);
+    }
+    return MGP_OK;
+}
+
+size_t workspace_bytes(uint32_t b_max)
+{
+    return kWsOffsetsOffset + (((size_t)b_max * 4u + 255u) & ~(size_t)255u);
+}
+
+int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,
+                            mgp_stats* st_user, hipStream_t stream)
+{
+    Partial* part = reinterpret_cast<Partial*>(ws + kWsPartialsOffset);
+    mgp_stats* st = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(ws + kWsOffsetsOffset);
+    const uint32_t g = reduce_blocks(n);
+    const uint32_t chunk = reduce_chunk(n, g);
+    if (((uintptr_t)w & 15u) == 0)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part);
+    int rc = check_launch("reduce kernel");
+    if (rc) return rc;
+    FinalizeArgs a;
+    a.n = n;
+    a.eps = p.eps;
+    a.B_user = p.B;
+    a.b_max = p.b_max;
+    a.make_offsets = make_offsets ? 1u : 0u;
+    a.key0 = (uint32_t)p.seed;
+    a.key1 = (uint32_t)(p.seed >> 32);
+    a.stream_id = p.stream_id;
+    a.tag = call_tag(n, p.variant, p.seed, p.stream_id);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kReduceThreads), 0, stream, part, g, a, st, st_user, offs);
+    return check_launch("finalize kernel");
+}
+
+template <int V>
+static void launch_loop(bool narrow, dim3 grid, hipStream_t s, const float* w, uint32_t n, const mgp_stats* st,
+                        const uint32_t* offs, uint32_t k0, uint32_t k1, uint32_t sid, uint32_t n_w,
+                        uint32_t n_part, uint32_t tag, uint32_t b_cap, int32_t* anc)
+{
+    if (narrow)
+        hipLaunchKernelGGL((k_resample<V, true>), grid, dim3(kLoopThreads), 0, s, w, n, st, offs, k0, k1, sid, n_w,
+                           n_part, tag, b_cap, anc);
+    else
+        hipLaunchKernelGGL((k_resample<V, false>), grid, dim3(kLoopThreads), 0, s, w, n, st, offs, k0, k1, sid, n_w,
+                           n_part, tag, b_cap, anc);
+}
+
+int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream)
+{
+    const mgp_stats* st = reinterpret_cast<const mgp_stats*>(ws + kWsStatsOffset);
+    const uint32_t* offs = reinterpret_cast<const uint32_t*>(ws + kWsOffsetsOffset);
+    const uint32_t n_w = p.partition_bytes / 4u;
+    const uint32_t n_part = (uint32_t)(((uint64_t)n + n_w - 1u) / n_w);
+    const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
+    const dim3 grid((n + kLoopThreads - 1u) / kLoopThreads);
+    const bool narrow = n <= (1u << 30);
+    const uint32_t tag = call_tag(n, p.variant, p.seed, p.stream_id);
+    const uint32_t cap = p.b_max;
+    switch (p.variant) {
+    case kMetropolis:
+        launch_loop<kMetropolis>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        break;
+    case kC1:
+        launch_loop<kC1>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        break;
+    case kC2:
+        launch_loop<kC2>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        break;
+    default:
+        launch_loop<kMegopolis>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        break;
+    }
+    return check_launch("resample kernel");
+}
+
+// One element (or float4) per thread up to 2^20 blocks, grid-stride beyond.
+static uint32_t gather_blocks(uint64_t total)
+{
+    const uint64_t b = (total + 255u) / 256u;
+    return (uint32_t)(b < (1u << 20) ? (b ? b : 1) : (1u << 20));
+}
+
+int enqueue_gather(const float* states, uint32_t n_states, uint32_t d, const int32_t* anc, uint32_t n_out,
+                   float* out, hipStream_t stream)
+{
+    if (n_out == 0) return MGP_OK;
+    const bool vec = (d % 4u == 0u) && (((uintptr_t)states & 15u) == 0) && (((uintptr_t)out & 15u) == 0);
+    if (vec) {
+        const uint32_t d4 = d / 4u;
+        const uint64_t total = (uint64_t)n_out * d4;
+        const dim3 grid(gather_blocks(total));
+        hipLaunchKernelGGL(k_gather_vec4, grid, dim3(256), 0, stream, reinterpret_cast<const float4*>(states),
+                           n_states, d4, anc, total, reinterpret_cast<float4*>(out));
+    } else {
+        const uint64_t total = (uint64_t)n_out * d;
+        const dim3 grid(gather_blocks(total));
+        hipLaunchKernelGGL(k_gather_scalar, grid, dim3(256), 0, stream, states, n_states, d, anc, total, out);
+    }
+    return check_launch("gather kernel");
+}
+
+}  // namespace mgp
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace mgp;
+
+extern "C" {
+
+const char* mgp_last_error(void) { return g_err; }
+
+int mgp_version(void) { return kVersion; }
+
+int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes)
+{
+    clear_error();
+    if (!bytes) return fail(MGP_EINVAL, "bytes is NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    Params p;
+    int rc = normalize_params(params, &p);
+    if (rc) return rc;
+    *bytes = workspace_bytes(p.b_max);
+    return MGP_OK;
+}
+
+static int check_workspace(void* ws, size_t ws_bytes, const Params& p)
+{
+    if (!ws) return fail(MGP_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(MGP_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = workspace_bytes(p.b_max);
+    if (ws_bytes < need) return fail(MGP_ERANGE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return MGP_OK;
+}
+
+int mgp_compute_B(const float* w_dev, int32_t n, const mgp_params* params, mgp_stats* stats_dev,
+                  void* workspace_dev, size_t workspace_bytes_, void* stream)
+{
+    clear_error();
+    if (!w_dev) return fail(MGP_EINVAL, "w_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    Params p;
+    int rc = normalize_params(params, &p);
+    if (rc) return rc;
+    rc = check_workspace(workspace_dev, workspace_bytes_, p);
+    if (rc) return rc;
+    return enqueue_reduce_finalize(w_dev, (uint32_t)n, p, p.variant == kMegopolis,
+                                   static_cast<char*>(workspace_dev), stats_dev, static_cast<hipStream_t>(stream));
+}
+
+int mgp_resample_prepared(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
+                          void* workspace_dev, size_t workspace_bytes_, void* stream)
+{
+    clear_error();
+    if (!w_dev || !ancestors_dev) return fail(MGP_EINVAL, "w_dev and ancestors_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    Params p;
+    int rc = normalize_params(params, &p);
+    if (rc) return rc;
+    rc = check_workspace(workspace_dev, workspace_bytes_, p);
+    if (rc) return rc;
+    return enqueue_loop(w_dev, (uint32_t)n, p, static_cast<char*>(workspace_dev), ancestors_dev,
+                        static_cast<hipStream_t>(stream));
+}
+
+int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
+                 mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes_, void* stream)
+{
+    clear_error();
+    if (!w_dev || !ancestors_dev) return fail(MGP_EINVAL, "w_dev and ancestors_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    Params p;
+    int rc = normalize_params(params, &p);
+    if (rc) return rc;
+    rc = check_workspace(workspace_dev, workspace_bytes_, p);
+    if (rc) return rc;
+    char* ws = static_cast<char*>(workspace_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = enqueue_reduce_finalize(w_dev, (uint32_t)n, p, p.variant == kMegopolis, ws, stats_dev, s);
+    if (rc) return rc;
+    return enqueue_loop(w_dev, (uint32_t)n, p, ws, ancestors_dev, s);
+}
+
+int mgp_gather(const float* states_dev, int32_t n_states, int32_t d, const int32_t* ancestors_dev, int32_t n_out,
+               float* out_dev, void* stream)
+{
+    clear_error();
+    if (!states_dev || !ancestors_dev || !out_dev) return fail(MGP_EINVAL, "NULL pointer argument");
+    if (n_states < 1 || d < 1 || n_out < 0) return fail(MGP_EINVAL, "need n_states >= 1, d >= 1, n_out >= 0");
+    const uint64_t in_bytes = (uint64_t)n_states * (uint64_t)d * 4u;
+    const uint64_t out_bytes = (uint64_t)n_out * (uint64_t)d * 4u;
+    const uintptr_t a0 = (uintptr_t)states_dev, a1 = a0 + in_bytes;
+    const uintptr_t b0 = (uintptr_t)out_dev, b1 = b0 + out_bytes;
+    if (out_bytes && a0 < b1 && b0 < a1) return fail(MGP_EINVAL, "out_dev overlaps states_dev");
+    return enqueue_gather(states_dev, (uint32_t)n_states, (uint32_t)d, ancestors_dev, (uint32_t)n_out, out_dev,
+                          static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""ctypes binding of libmgp (include/mgp.h).
+
+The mgp_* functions mirror the C entry points one to one and take raw device
+pointers (ints); they only marshal arguments and turn negative return codes
+into MgpError. The helpers below them (Resampler, resample, gather) allocate
+the device tensors with torch and call the same entry points; every step of
+the computation runs in the HIP kernels of libmgp.so.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmgp.so")
+
+MGP_OK, MGP_EINVAL, MGP_ERANGE, MGP_ENOMEM, MGP_EHIP, MGP_EBUSY, MGP_EWEIGHTS = 0, -1, -2, -3, -4, -5, -6
+MGP_METROPOLIS, MGP_C1, MGP_C2, MGP_MEGOPOLIS = 0, 1, 2, 3
+VARIANTS = {"metropolis": MGP_METROPOLIS, "c1": MGP_C1, "c2": MGP_C2, "megopolis": MGP_MEGOPOLIS}
+
+
+class MgpError(RuntimeError):
+    def __init__(self, code: int, func: str, message: str):
+        super().__init__(f"{func} failed ({code}): {message}")
+        self.code = code
+
+
+class mgp_params(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("B", ctypes.c_uint32), ("epsilon", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("partition_bytes", ctypes.c_uint32),
+                ("b_max", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class mgp_stats(ctypes.Structure):
+    _fields_ = [("w_sum", ctypes.c_double), ("ratio", ctypes.c_double), ("b_raw", ctypes.c_double),
+                ("w_max", ctypes.c_float), ("B", ctypes.c_uint32), ("clamped", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("n", ctypes.c_uint32), ("tag", ctypes.c_uint32)]
+
+
+STATS_BYTES = ctypes.sizeof(mgp_stats)
+STATS_DTYPE = np.dtype([("w_sum", "<f8"), ("ratio", "<f8"), ("b_raw", "<f8"), ("w_max", "<f4"), ("B", "<u4"),
+                        ("clamped", "<u4"), ("status", "<i4"), ("n", "<u4"), ("tag", "<u4")])
+assert STATS_DTYPE.itemsize == STATS_BYTES == 48
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded libmgp.so. Raises if the HIP library has not been built:
+    there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(mgp_params)
+        L.mgp_workspace_size.argtypes = [ctypes.c_int32, P, ctypes.POINTER(ctypes.c_size_t)]
+        L.mgp_resample.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.mgp_compute_B.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
+        L.mgp_resample_prepared.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
+        L.mgp_gather.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+        L.mgp_last_error.argtypes = []
+        L.mgp_last_error.restype = ctypes.c_char_p
+        L.mgp_version.argtypes = []
+        for f in ("mgp_workspace_size", "mgp_resample", "mgp_compute_B", "mgp_resample_prepared", "mgp_gather",
+                  "mgp_version"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, func: str) -> int:
+    if rc < 0:
+        raise MgpError(rc, func, (lib().mgp_last_error() or b"").decode())
+    return rc
+
+
+def make_params(variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
+                partition_bytes: int = 128, b_max: int = 0) -> mgp_params:
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    return mgp_params(v, int(B), float(epsilon), int(seed) & (2**64 - 1), int(stream_id), int(partition_bytes),
+                      int(b_max), 0)
+
+
+# ---------------------------------------------------------------------------
+# C entry points, same names
+# ---------------------------------------------------------------------------
+
+def mgp_version() -> int:
+    return lib().mgp_version()
+
+
+def mgp_last_error() -> str:
+    return (lib().mgp_last_error() or b"").decode()
+
+
+def mgp_workspace_size(n: int, params: mgp_params) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().mgp_workspace_size(n, ctypes.byref(params), ctypes.byref(out)), "mgp_workspace_size")
+    return out.value
+
+
+def mgp_resample(w_dev: int, n: int, params: mgp_params, ancestors_dev: int, stats_dev: int, workspace_dev: int,
+                 workspace_bytes: int, stream: int) -> None:
+    _check(lib().mgp_resample(w_dev, n, ctypes.byref(params), ancestors_dev, stats_dev or None, workspace_dev,
+                              workspace_bytes, stream or None), "mgp_resample")
+
+
+def mgp_compute_B(w_dev: int, n: int, params: mgp_params, stats_dev: int, workspace_dev: int,
+                  workspace_bytes: int, stream: int) -> None:
+    _check(lib().mgp_compute_B(w_dev, n, ctypes.byref(params), stats_dev or None, workspace_dev, workspace_bytes,
+                               stream or None), "mgp_compute_B")
+
+
+def mgp_resample_prepared(w_dev: int, n: int, params: mgp_params, ancestors_dev: int, workspace_dev: int,
+                          workspace_bytes: int, stream: int) -> None:
+    _check(lib().mgp_resample_prepared(w_dev, n, ctypes.byref(params), ancestors_dev, workspace_dev,
+                                       workspace_bytes, stream or None), "mgp_resample_prepared")
+
+
+def mgp_gather(states_dev: int, n_states: int, d: int, ancestors_dev: int, n_out: int, out_dev: int,
+               stream: int) -> None:
+    _check(lib().mgp_gather(states_dev, n_states, d, ancestors_dev, n_out, out_dev, stream or None), "mgp_gather")
+
+
+# ---------------------------------------------------------------------------
+# torch helpers
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream() -> int:
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def decode_stats(stats_tensor) -> dict:
+    raw = stats_tensor.detach().cpu().numpy().tobytes()
+    rec = np.frombuffer(raw[:STATS_BYTES], dtype=STATS_DTYPE)[0]
+    return {k: rec[k].item() for k in STATS_DTYPE.names}
+
+
+class Resampler:
+    """Holds a device workspace sized for (n_max, b_max) and calls mgp_resample."""
+
+    def __init__(self, n_max: int, b_max: int = 0, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.b_max = b_max
+        self.ws_bytes = mgp_workspace_size(max(1, n_max), make_params(b_max=b_max))
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=self.device)
+
+    def resample(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
+                 stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+        torch = _torch()
+        assert w.dtype == torch.float32 and w.is_cuda and w.is_contiguous() and w.dim() == 1
+        n = w.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=w.device)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        mgp_resample(w.data_ptr(), n, p, out.data_ptr(), self.stats.data_ptr(), self.workspace.data_ptr(),
+                     self.ws_bytes, current_stream() if stream is None else stream)
+        return out
+
+    def compute_B(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
+                  stream_id: int = 0, partition_bytes: int = 128, stream: int | None = None) -> None:
+        """Reduction, B and offsets only (asynchronous; read last_stats() after a sync)."""
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        mgp_compute_B(w.data_ptr(), w.numel(), p, self.stats.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
+                      current_stream() if stream is None else stream)
+
+    def resample_prepared(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
+                          stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+        """The accept loop only, after compute_B with the same arguments."""
+        torch = _torch()
+        n = w.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=w.device)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        mgp_resample_prepared(w.data_ptr(), n, p, out.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
+                              current_stream() if stream is None else stream)
+        return out
+
+    def last_stats(self) -> dict:
+        return decode_stats(self.stats)
+
+
+def resample(w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
+             partition_bytes: int = 128, b_max: int = 0):
+    """One-shot resample of a device weight vector; returns (ancestors, stats dict)."""
+    r = Resampler(w.numel(), b_max, w.device)
+    anc = r.resample(w, variant, B, epsilon, seed, stream_id, partition_bytes)
+    return anc, r.last_stats()
+
+
+def gather(states, anc, out=None, stream: int | None = None):
+    """out[i] = states[anc[i]] for fp32 states [n_states, d] on the device."""
+    torch = _torch()
+    assert states.dtype == torch.float32 and states.is_cuda and states.is_contiguous()
+    st2 = states.view(states.shape[0], -1)
+    n_states, d = st2.shape
+    n_out = anc.numel()
+    if out is None:
+        out = torch.empty((n_out, d), dtype=torch.float32, device=states.device)
+    mgp_gather(st2.data_ptr(), n_states, d, anc.data_ptr(), n_out, out.data_ptr(),
+               current_stream() if stream is None else stream)
+    return out

@@ -1,0 +1,81 @@
+"""CPU-only checks of the HIP library's C ABI: it loads, exports every entry
+point include/mgp.h declares, and answers the host-only calls (no device
+work is launched here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgp.h")
+
+
+@pytest.fixture(scope="module")
+def mgp():
+    from paper_2109_13504_amd import mgp as m
+    from paper_2109_13504_amd.csrc import build as b
+    if b.needs_build():
+        b.build()
+    m.lib()
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mgp_[A-Za-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("mgp_resample", "mgp_gather", "mgp_compute_B", "mgp_workspace_size", "mgp_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(mgp):
+    out = subprocess.run(["nm", "-D", "--defined-only", mgp.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(mgp.LIB_PATH)
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_struct_layouts_match_header(mgp):
+    assert ctypes.sizeof(mgp.mgp_params) == 40
+    assert ctypes.sizeof(mgp.mgp_stats) == 48
+
+
+def test_workspace_size_host_only(mgp):
+    small = mgp.mgp_workspace_size(100, mgp.make_params(b_max=16))
+    big = mgp.mgp_workspace_size(100, mgp.make_params(b_max=65536))
+    assert big >= small + 4 * (65536 - 16) - 256
+    assert small % 256 == 0
+
+
+def test_argument_errors_before_any_device_call(mgp):
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_workspace_size(0, mgp.make_params())
+    assert e.value.code == mgp.MGP_EINVAL
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_workspace_size(10, mgp.make_params(variant=7))
+    assert e.value.code == mgp.MGP_EINVAL
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_workspace_size(10, mgp.make_params(B=100, b_max=50))
+    assert e.value.code == mgp.MGP_ERANGE
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_resample(0, 10, mgp.make_params(), 0, 0, 0, 0, 0)
+    assert e.value.code == mgp.MGP_EINVAL
+    assert "NULL" in mgp.mgp_last_error()
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_gather(0, 10, 4, 0, 10, 0, 0)
+    assert e.value.code == mgp.MGP_EINVAL
+
+
+def test_version(mgp):
+    assert mgp.mgp_version() >= 100
