@@ -48,18 +48,36 @@ struct Words {
     uint32_t x0, x1, x2, x3;
 };
 
-// Philox4x32-10 on counter (c0, c1, c2, c3) with key (k0, k1).
+// a ^ b ^ c in one VALU instruction (gfx950 three-input bitwise op, truth
+// table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Philox4x32-10 on counter (c0, c1, c2, c3) with key (k0, k1). Each round
+// takes both 32x32 -> 64-bit products as one v_mad_u64_u32 each. With the
+// per-lane index in c3 and the other words wave-uniform, rounds 1-3 still
+// hold uniform values that the compiler keeps on the scalar unit, so those
+// use plain xors; from round 4 on every word is per lane and each pair of
+// xors is one three-input op.
 __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                         uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(kPhiloxM0, c0);
-        const uint32_t lo0 = kPhiloxM0 * c0;
-        const uint32_t hi1 = __umulhi(kPhiloxM1, c2);
-        const uint32_t lo1 = kPhiloxM1 * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0, n2;
+        if (r < 3) {
+            n0 = hi1 ^ c1 ^ k0;
+            n2 = hi0 ^ c3 ^ k1;
+        } else {
+            n0 = xor3(hi1, c1, k0);
+            n2 = xor3(hi0, c3, k1);
+        }
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -252,6 +270,97 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
         }
     }
     return k;
+}
+
+// ---------------------------------------------------------------------------
+// Megopolis over a mirrored weight array.
+//
+// M[k] = w[k mod n] for k < 2n + kMirrorPad. The candidate of Algorithm 5,
+// (i_aligned + o_aligned + (i + o) mod 32) mod N, is then simply
+// M[i_aligned + o_aligned + (i + o) mod 32]: the sum is at most 2n - 2 for a
+// real particle, so the mod N moves from every load to the one final
+// ancestor. Each thread carries P particles i0 + 256 p; they share i mod 32,
+// so all P candidates of a step are the slot-0 candidate plus 256 p, and the
+// P loads differ only in their immediate byte offset (1024 p).
+// Byte offsets must fit 32 bits: 4 (2n + kMirrorPad) < 2^32.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMirrorPad = 2048;             // >= 256 P + 32 for P <= 4
+constexpr uint32_t kMirrorMaxN = (1u << 29) - 4096;
+
+template <int P>
+__device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ M, const uint32_t* __restrict__ offs,
+                                                       uint32_t n, uint32_t B, uint32_t key0, uint32_t key1,
+                                                       uint32_t stream_id, uint32_t i0, uint32_t (&anc_out)[P])
+{
+    constexpr uint32_t kStrideBytes = 4u * 256u;  // particle p sits 256 particles after p - 1
+    const uint32_t ia4 = (i0 & ~(kSegment - 1u)) * 4u;
+    const uint32_t il4 = (i0 & (kSegment - 1u)) * 4u;
+    uint32_t kk[P];  // ancestor as the slot-0 byte offset into M
+    float wk[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        kk[p] = i0 * 4u;
+        wk[p] = *reinterpret_cast<const float*>(M + i0 * 4u + kStrideBytes * p);
+    }
+    const uint32_t nblk = B / 5u;
+    for (uint32_t q = 0; q < nblk; ++q) {
+        uint32_t jb[5];
+        float wj[5][P];
+#pragma unroll
+        for (uint32_t s = 0; s < 5; ++s) {
+            uint32_t o = offs[q * 5u + s];
+            o = o < n ? o : n - 1u;
+            const uint32_t oa4 = (o & ~(kSegment - 1u)) * 4u;
+            const uint32_t t4 = (il4 + (o & (kSegment - 1u)) * 4u) & ((kSegment - 1u) * 4u);
+            const uint32_t voff = ia4 | t4;
+            const char* base = M + oa4;
+#pragma unroll
+            for (int p = 0; p < P; ++p) wj[s][p] = *reinterpret_cast<const float*>(base + voff + kStrideBytes * p);
+            jb[s] = voff + oa4;
+        }
+        UBlock ub[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) ub[p] = u_block(philox(q, kTagU, stream_id, i0 + 256u * p, key0, key1));
+#pragma unroll
+        for (uint32_t s = 0; s < 5; ++s) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float prod = ub[p].u[s] * wk[p];
+                const bool acc = prod <= wj[s][p];
+                kk[p] = acc ? jb[s] : kk[p];
+                wk[p] = acc ? wj[s][p] : wk[p];
+            }
+        }
+    }
+    // remaining B mod 5 steps
+    if (nblk * 5u < B) {
+        UBlock ub[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) ub[p] = u_block(philox(nblk, kTagU, stream_id, i0 + 256u * p, key0, key1));
+        for (uint32_t b = nblk * 5u; b < B; ++b) {
+            uint32_t o = offs[b];
+            o = o < n ? o : n - 1u;
+            const uint32_t oa4 = (o & ~(kSegment - 1u)) * 4u;
+            const uint32_t t4 = (il4 + (o & (kSegment - 1u)) * 4u) & ((kSegment - 1u) * 4u);
+            const uint32_t voff = ia4 | t4;
+            const char* base = M + oa4;
+            const uint32_t r = b - nblk * 5u;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float wjv = *reinterpret_cast<const float*>(base + voff + kStrideBytes * p);
+                const float u = r == 0 ? ub[p].u[0] : r == 1 ? ub[p].u[1] : r == 2 ? ub[p].u[2] : ub[p].u[3];
+                const float prod = u * wk[p];
+                const bool acc = prod <= wjv;
+                kk[p] = acc ? voff + oa4 : kk[p];
+                wk[p] = acc ? wjv : wk[p];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        uint32_t k = kk[p] / 4u + 256u * p;
+        anc_out[p] = k >= n ? k - n : k;
+    }
 }
 
 }  // namespace mgp

@@ -20,8 +20,10 @@ constexpr uint32_t kBMaxLimit = 1u << 24;
 
 // Workspace layout of a single-filter call (byte offsets, 256-aligned):
 //   [stats: mgp_stats][partials: kMaxPartials x Partial][offsets: b_max x u32]
+//   [mirror: (2n + kMirrorPad) x f32, Megopolis with n <= kMirrorMaxN only]
 constexpr size_t kWsStatsOffset = 0;
 constexpr size_t kWsPartialsOffset = 256;
+constexpr int kMegopolisPPT = 4;  // particles per thread of the mirrored Megopolis loop
 
 struct Partial {
     double w_sum;
@@ -68,6 +70,9 @@ void clear_error();
 int check_launch(const char* what);
 int normalize_params(const mgp_params* in, Params* out);
 size_t workspace_bytes(uint32_t b_max);
+size_t workspace_bytes(uint32_t n, const Params& p);
+bool uses_mirror(uint32_t n, int variant);
+size_t mirror_offset(uint32_t b_max);
 uint32_t reduce_blocks(uint32_t n);
 uint32_t reduce_chunk(uint32_t n, uint32_t blocks);
 int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,

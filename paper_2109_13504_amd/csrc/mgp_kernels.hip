@@ -82,10 +82,14 @@ __device__ void block_reduce(float& mx, double& s, uint32_t& bad)
 }
 
 // Block b reduces w[b*chunk, min(n, (b+1)*chunk)); chunk is a multiple of 4
-// and, with Vec, w is 16-byte aligned so float4 loads stay aligned.
+// and, with Vec, w is 16-byte aligned so float4 loads stay aligned. With a
+// mirror, the block also writes M[i] = M[i + n] = w[i] for its range, and
+// block 0 writes the padding M[2n + k] = w[k mod n]; Vec then also needs
+// n % 4 == 0 so that the second copy stays 16-byte aligned.
 template <bool Vec>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* __restrict__ w, uint32_t n,
-                                                           uint32_t chunk, Partial* __restrict__ part)
+                                                           uint32_t chunk, Partial* __restrict__ part,
+                                                           float* __restrict__ mirror)
 {
     // trailing blocks may start at or past n when chunk was rounded up: their
     // range is empty and they contribute the neutral partial
@@ -99,14 +103,35 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* __restri
         const uint64_t end4 = start + ((end - start) & ~(uint64_t)3);
         for (uint64_t i = start + 4ull * threadIdx.x; i < end4; i += 4ull * blockDim.x) {
             const float4 v = *reinterpret_cast<const float4*>(w + i);
+            if (mirror) {
+                *reinterpret_cast<float4*>(mirror + i) = v;
+                *reinterpret_cast<float4*>(mirror + n + i) = v;
+            }
             fold(v.x, mx, s, bad);
             fold(v.y, mx, s, bad);
             fold(v.z, mx, s, bad);
             fold(v.w, mx, s, bad);
         }
-        for (uint64_t i = end4 + threadIdx.x; i < end; i += blockDim.x) fold(w[i], mx, s, bad);
+        for (uint64_t i = end4 + threadIdx.x; i < end; i += blockDim.x) {
+            const float v = w[i];
+            if (mirror) {
+                mirror[i] = v;
+                mirror[n + i] = v;
+            }
+            fold(v, mx, s, bad);
+        }
     } else {
-        for (uint64_t i = start + threadIdx.x; i < end; i += blockDim.x) fold(w[i], mx, s, bad);
+        for (uint64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
+            const float v = w[i];
+            if (mirror) {
+                mirror[i] = v;
+                mirror[n + i] = v;
+            }
+            fold(v, mx, s, bad);
+        }
+    }
+    if (mirror && blockIdx.x == 0) {
+        for (uint32_t k = threadIdx.x; k < kMirrorPad; k += blockDim.x) mirror[2ull * n + k] = w[k % n];
     }
     block_reduce(mx, s, bad);
     if (threadIdx.x == 0) part[blockIdx.x] = Partial{s, mx, bad};
@@ -217,6 +242,33 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
     anc[i] = (int32_t)run_chain<V, Narrow>(P, i);
 }
 
+// Megopolis over the mirrored weights, kMegopolisPPT particles per thread.
+template <int P>
+__global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* __restrict__ mirror, uint32_t n,
+                                                                   const mgp_stats* __restrict__ st,
+                                                                   const uint32_t* __restrict__ offsets,
+                                                                   uint32_t key0, uint32_t key1, uint32_t stream_id,
+                                                                   uint32_t tag, uint32_t b_cap,
+                                                                   int32_t* __restrict__ anc)
+{
+    const uint32_t i0 = blockIdx.x * (kLoopThreads * P) + threadIdx.x;
+    const uint32_t B = st->B;
+    const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    if (!ok) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (i0 + kLoopThreads * p < n) anc[i0 + kLoopThreads * p] = -1;
+        return;
+    }
+    // every lane runs, also past n: the mirror's padding keeps those loads in
+    // bounds, and only real particles store
+    uint32_t k[P];
+    megopolis_mirror_chain<P>(reinterpret_cast<const char*>(mirror), offsets, n, B, key0, key1, stream_id, i0, k);
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (i0 + kLoopThreads * p < n) anc[i0 + kLoopThreads * p] = (int32_t)k[p];
+}
+
 // ---------------------------------------------------------------------------
 // 4. Gather: out[i] = states[anc[i]] (rows of d fp32). With d % 4 == 0 and
 //    16-byte aligned rows every thread copies one float4; otherwise one
@@ -303,18 +355,32 @@ size_t workspace_bytes(uint32_t b_max)
     return kWsOffsetsOffset + (((size_t)b_max * 4u + 255u) & ~(size_t)255u);
 }
 
+bool uses_mirror(uint32_t n, int variant) { return variant == kMegopolis && n <= kMirrorMaxN; }
+
+size_t mirror_offset(uint32_t b_max) { return workspace_bytes(b_max); }
+
+size_t workspace_bytes(uint32_t n, const Params& p)
+{
+    size_t b = workspace_bytes(p.b_max);
+    if (uses_mirror(n, p.variant)) b += (((size_t)2 * n + kMirrorPad) * 4u + 255u) & ~(size_t)255u;
+    return b;
+}
+
 int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,
                             mgp_stats* st_user, hipStream_t stream)
 {
     Partial* part = reinterpret_cast<Partial*>(ws + kWsPartialsOffset);
     mgp_stats* st = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
     uint32_t* offs = reinterpret_cast<uint32_t*>(ws + kWsOffsetsOffset);
+    float* mirror = (make_offsets && uses_mirror(n, p.variant)) ? reinterpret_cast<float*>(ws + mirror_offset(p.b_max))
+                                                                  : nullptr;
     const uint32_t g = reduce_blocks(n);
     const uint32_t chunk = reduce_chunk(n, g);
-    if (((uintptr_t)w & 15u) == 0)
-        hipLaunchKernelGGL(k_reduce<true>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part);
+    const bool vec = (((uintptr_t)w & 15u) == 0) && (!mirror || n % 4u == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part, mirror);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part);
+        hipLaunchKernelGGL(k_reduce<false>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part, mirror);
     int rc = check_launch("reduce kernel");
     if (rc) return rc;
     FinalizeArgs a;
@@ -355,6 +421,14 @@ int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t*
     const bool narrow = n <= (1u << 30);
     const uint32_t tag = call_tag(n, p.variant, p.seed, p.stream_id);
     const uint32_t cap = p.b_max;
+    if (uses_mirror(n, p.variant)) {
+        constexpr int P = kMegopolisPPT;
+        const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
+        const dim3 g((n + kLoopThreads * P - 1u) / (kLoopThreads * P));
+        hipLaunchKernelGGL((k_megopolis_mirror<P>), g, dim3(kLoopThreads), 0, stream, mirror, n, st, offs, k0, k1,
+                           p.stream_id, tag, cap, anc);
+        return check_launch("megopolis kernel");
+    }
     switch (p.variant) {
     case kMetropolis:
         launch_loop<kMetropolis>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
@@ -419,15 +493,15 @@ int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes)
     Params p;
     int rc = normalize_params(params, &p);
     if (rc) return rc;
-    *bytes = workspace_bytes(p.b_max);
+    *bytes = workspace_bytes((uint32_t)n, p);
     return MGP_OK;
 }
 
-static int check_workspace(void* ws, size_t ws_bytes, const Params& p)
+static int check_workspace(void* ws, size_t ws_bytes, uint32_t n, const Params& p)
 {
     if (!ws) return fail(MGP_EINVAL, "workspace is NULL");
     if (((uintptr_t)ws & 255u) != 0) return fail(MGP_EINVAL, "workspace must be 256-byte aligned");
-    const size_t need = workspace_bytes(p.b_max);
+    const size_t need = workspace_bytes(n, p);
     if (ws_bytes < need) return fail(MGP_ERANGE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     return MGP_OK;
 }
@@ -441,7 +515,7 @@ int mgp_compute_B(const float* w_dev, int32_t n, const mgp_params* params, mgp_s
     Params p;
     int rc = normalize_params(params, &p);
     if (rc) return rc;
-    rc = check_workspace(workspace_dev, workspace_bytes_, p);
+    rc = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
     if (rc) return rc;
     return enqueue_reduce_finalize(w_dev, (uint32_t)n, p, p.variant == kMegopolis,
                                    static_cast<char*>(workspace_dev), stats_dev, static_cast<hipStream_t>(stream));
@@ -456,7 +530,7 @@ int mgp_resample_prepared(const float* w_dev, int32_t n, const mgp_params* param
     Params p;
     int rc = normalize_params(params, &p);
     if (rc) return rc;
-    rc = check_workspace(workspace_dev, workspace_bytes_, p);
+    rc = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
     if (rc) return rc;
     return enqueue_loop(w_dev, (uint32_t)n, p, static_cast<char*>(workspace_dev), ancestors_dev,
                         static_cast<hipStream_t>(stream));
@@ -471,7 +545,7 @@ int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_
     Params p;
     int rc = normalize_params(params, &p);
     if (rc) return rc;
-    rc = check_workspace(workspace_dev, workspace_bytes_, p);
+    rc = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
     if (rc) return rc;
     char* ws = static_cast<char*>(workspace_dev);
     hipStream_t s = static_cast<hipStream_t>(stream);
