@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-metropolis", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=16, help="oracle runs every k-th particle's chain")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-filters section")
+    ap.add_argument("--batch-runs", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
     return ap.parse_args()
@@ -119,6 +121,68 @@ def cpu_baseline(w_np, variant, eps, stride):
     return {"value": idx.size / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"single-threaded C oracle: fp64 reduction + B over all {n} weights, then the B-step chains "
                       f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s"}
+
+
+def batched_section(torch, mgp, inputs, runs):
+    """512 filters, N_f = round(2^U(10, 18)), y_f ~ U[0, 4], D = 4, Megopolis:
+    one graph launch per run against the same filters as 512 per-filter
+    launch sequences (reduce, finalize, loop, gather) issued from C."""
+    import tempfile
+
+    import numpy as np
+    dev = torch.device("cuda:0")
+    sizes, ys = inputs.batch_filters()
+    fl = []
+    for f, (n, y) in enumerate(zip(sizes, ys)):
+        w, st = inputs.gaussian_weights_and_states(int(n), float(y), 4, f)
+        fl.append({"w": torch.from_numpy(w).to(dev), "anc": torch.empty(int(n), dtype=torch.int32, device=dev),
+                   "states": torch.from_numpy(st).to(dev), "out": torch.empty((int(n), 4), device=dev),
+                   "seed": 777000 + f, "stream_id": f, "epsilon": 0.01})
+    cache = os.path.join(tempfile.gettempdir(), "mgp_batch_tune.txt")
+    t0 = time.perf_counter()
+    plan = mgp.BatchPlan(fl, "megopolis", d=4, tune_cache=cache)
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) * 1000.0 / k
+        per = [a.elapsed_time(b) for a, b in evs]
+        return wall, per
+
+    g_wall, g_per = timed(plan.run, runs)
+    s_wall, s_per = timed(plan.run_separate, max(3, runs // 4))
+    total_n = int(np.sum(sizes))
+    steps = info["est_particle_steps"]
+    plan.close()
+    return {
+        "workload": "512 filters, N_f=round(2^U(10,18)), y_f~U[0,4], eps=0.01, Megopolis, fused gather D=4",
+        "particles": total_n,
+        "particle_steps": steps,
+        "graph_ms": g_wall,
+        "graph_p50_ms": pct(g_per, 50),
+        "graph_p99_ms": pct(g_per, 99),
+        "separate_ms": s_wall,
+        "separate_p50_ms": pct(s_per, 50),
+        "separate_p99_ms": pct(s_per, 99),
+        "speedup_vs_separate": s_wall / g_wall,
+        "particles_per_s": total_n / (g_wall * 1e-3),
+        "effective_weight_GBs": 4.0 * steps / (g_wall * 1e-3) / 1e9,
+        "tuned_shape": {"block_threads": info["block_threads"], "particles_per_thread": info["particles_per_thread"],
+                        "schedule": "grid" if info["schedule"] == 1 else "persistent",
+                        "from_cache": bool(info["from_cache"])},
+        "plan_create_s": plan_s,
+    }
 
 
 def main():
@@ -213,6 +277,13 @@ def main():
                                 "p99_ms": pct(per_m["total"], 99)}
         result["speedup_vs_metropolis"] = ms_m / ms
         log(f"[bench] metropolis: {ms_m:.3f} ms/step, loop {lm:.3f} ms -> speedup {ms_m / ms:.2f}x")
+
+    if not args.no_batched:
+        log("[bench] batched: 512 filters")
+        result["batched"] = batched_section(torch, mgp, inputs, args.batch_runs)
+        bt = result["batched"]
+        log(f"[bench] batched: graph {bt['graph_ms']:.3f} ms/run, separate {bt['separate_ms']:.3f} ms/run "
+            f"-> {bt['speedup_vs_separate']:.2f}x, shape {bt['tuned_shape']}")
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -123,6 +123,80 @@ int mgp_resample_prepared(const float* w_dev, int32_t n, const mgp_params* param
 int mgp_gather(const float* states_dev, int32_t n_states, int32_t d, const int32_t* ancestors_dev,
                int32_t n_out, float* out_dev, void* stream);
 
+/* ---- batched filters ----------------------------------------------------
+ * Many independent filters of uneven size resampled by one graph launch.
+ * Each filter's result is exactly that of mgp_resample (+ mgp_gather) with
+ * the same weights, B / epsilon, seed and stream_id: the batch changes the
+ * schedule, never the numbers. The paper's kernels resample one filter per
+ * launch and note that launch overhead dominates small N (Section 6.2);
+ * this mode removes it for many small filters. */
+typedef struct mgp_filter_desc {
+    const float* w_dev;          /* n fp32 weights (device) */
+    int32_t n;                   /* particles, 1 <= n <= 2^29 - 4096 */
+    uint32_t B;                  /* > 0: iterations; 0: from epsilon */
+    double epsilon;              /* bias bound in (0, 1] when B == 0 */
+    uint64_t seed;               /* Philox key of this filter */
+    uint32_t stream_id;          /* Philox stream of this filter */
+    uint32_t reserved;           /* must be 0 */
+    int32_t* ancestors_dev;      /* n int32 (device), written */
+    const float* states_dev;     /* n x d fp32 (device) or NULL: no gather for this filter */
+    float* out_states_dev;       /* n x d fp32 (device), written when states_dev is set */
+    mgp_stats* stats_dev;        /* device stats of this filter, or NULL */
+} mgp_filter_desc;
+
+typedef struct mgp_batch_config {
+    int32_t variant;             /* mgp_variant, shared by every filter */
+    int32_t d;                   /* state dimension of the fused gather (0: no gather) */
+    uint32_t partition_bytes;    /* C1/C2; 0 means 128 */
+    uint32_t b_max;              /* per-filter clamp / limit of B; 0 means 65536 */
+    int32_t block_threads;       /* 64, 128 or 256; 0: autotune */
+    int32_t particles_per_thread;/* 1, 2 or 4 (Megopolis; others use 1); 0: autotune */
+    int32_t schedule;            /* 1: one block per tile; 2: persistent blocks on per-XCD queues; 0: autotune */
+    int32_t use_graph;           /* 1: one hipGraph launch per run; 0: three plain launches */
+    const char* tune_cache;      /* autotuner cache file (read and updated), or NULL */
+} mgp_batch_config;
+
+typedef struct mgp_batch_info {
+    int32_t filters;
+    int32_t block_threads;
+    int32_t particles_per_thread;
+    int32_t schedule;
+    int32_t from_cache;          /* 1 if the tuning came from tune_cache */
+    int32_t xcds;                /* XCDs the tile order was balanced over */
+    int64_t particles;           /* sum of n */
+    int64_t tiles;               /* accept-loop tiles */
+    int64_t device_bytes;        /* device memory owned by the plan */
+    double est_particle_steps;   /* sum of n * B from the plan-time reduction */
+} mgp_batch_info;
+
+typedef struct mgp_batch_plan mgp_batch_plan;
+
+/* Builds a plan: validates the descriptors, allocates the plan's device
+ * memory (per-filter stats, partials, offsets, mirrors, tile tables), runs
+ * the reduction once on `stream` to estimate each filter's B (for load
+ * balance only), picks the launch shape (autotuning when asked) and captures
+ * the run into a hipGraph. Synchronises `stream`. Caller keeps the filters'
+ * buffers alive for the plan's lifetime. */
+int mgp_batch_plan_create(const mgp_filter_desc* filters, int32_t count, const mgp_batch_config* config,
+                          void* stream, mgp_batch_plan** plan);
+
+/* Replaces every filter's seed (count entries, host) for the following runs;
+ * the copy is enqueued on `stream`. */
+int mgp_batch_set_seeds(mgp_batch_plan* plan, const uint64_t* seeds, void* stream);
+
+/* Runs the batch: reduction, B and offsets for every filter, then the accept
+ * loops and fused gathers, as one graph launch on `stream`. */
+int mgp_batch_run(mgp_batch_plan* plan, void* stream);
+
+/* The comparison path: the same filters as one mgp_resample (+ mgp_gather)
+ * launch sequence per filter, on `stream`, into the same outputs. */
+int mgp_batch_run_separate(mgp_batch_plan* plan, void* stream);
+
+int mgp_batch_plan_info(const mgp_batch_plan* plan, mgp_batch_info* info);
+
+/* Frees the plan's device memory and graph. The plan must be idle. */
+int mgp_batch_plan_destroy(mgp_batch_plan* plan);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* mgp_last_error(void);
 

@@ -279,20 +279,23 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
 // (i_aligned + o_aligned + (i + o) mod 32) mod N, is then simply
 // M[i_aligned + o_aligned + (i + o) mod 32]: the sum is at most 2n - 2 for a
 // real particle, so the mod N moves from every load to the one final
-// ancestor. Each thread carries P particles i0 + 256 p; they share i mod 32,
-// so all P candidates of a step are the slot-0 candidate plus 256 p, and the
-// P loads differ only in their immediate byte offset (1024 p).
+// ancestor. Each thread carries P particles i0 + BT p (BT = block size);
+// they share i mod 32, so all P candidates of a step are the slot-0
+// candidate plus BT p, and the P loads differ only in their immediate byte
+// offset (4 BT p).
 // Byte offsets must fit 32 bits: 4 (2n + kMirrorPad) < 2^32.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMirrorPad = 2048;             // >= 256 P + 32 for P <= 4
 constexpr uint32_t kMirrorMaxN = (1u << 29) - 4096;
 
-template <int P>
+template <int P, int BT = 256>
 __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ M, const uint32_t* __restrict__ offs,
                                                        uint32_t n, uint32_t B, uint32_t key0, uint32_t key1,
                                                        uint32_t stream_id, uint32_t i0, uint32_t (&anc_out)[P])
 {
-    constexpr uint32_t kStrideBytes = 4u * 256u;  // particle p sits 256 particles after p - 1
+    static_assert(BT % 64 == 0 && BT * P + kSegment <= kMirrorPad, "particles of a thread must fit the padding");
+    static_assert(4 * BT * (P - 1) < 4096, "the immediate offset of the last particle must fit 12 bits");
+    constexpr uint32_t kStrideBytes = 4u * BT;  // particle p sits BT particles after p - 1
     const uint32_t ia4 = (i0 & ~(kSegment - 1u)) * 4u;
     const uint32_t il4 = (i0 & (kSegment - 1u)) * 4u;
     uint32_t kk[P];  // ancestor as the slot-0 byte offset into M
@@ -320,7 +323,7 @@ __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ 
         }
         UBlock ub[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) ub[p] = u_block(philox(q, kTagU, stream_id, i0 + 256u * p, key0, key1));
+        for (int p = 0; p < P; ++p) ub[p] = u_block(philox(q, kTagU, stream_id, i0 + BT * p, key0, key1));
 #pragma unroll
         for (uint32_t s = 0; s < 5; ++s) {
 #pragma unroll
@@ -336,7 +339,7 @@ __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ 
     if (nblk * 5u < B) {
         UBlock ub[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) ub[p] = u_block(philox(nblk, kTagU, stream_id, i0 + 256u * p, key0, key1));
+        for (int p = 0; p < P; ++p) ub[p] = u_block(philox(nblk, kTagU, stream_id, i0 + BT * p, key0, key1));
         for (uint32_t b = nblk * 5u; b < B; ++b) {
             uint32_t o = offs[b];
             o = o < n ? o : n - 1u;
@@ -358,7 +361,7 @@ __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ 
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        uint32_t k = kk[p] / 4u + 256u * p;
+        uint32_t k = kk[p] / 4u + BT * p;
         anc_out[p] = k >= n ? k - n : k;
     }
 }

@@ -39,6 +39,27 @@ class mgp_stats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("n", ctypes.c_uint32), ("tag", ctypes.c_uint32)]
 
 
+class mgp_filter_desc(ctypes.Structure):
+    _fields_ = [("w_dev", ctypes.c_void_p), ("n", ctypes.c_int32), ("B", ctypes.c_uint32),
+                ("epsilon", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("ancestors_dev", ctypes.c_void_p), ("states_dev", ctypes.c_void_p),
+                ("out_states_dev", ctypes.c_void_p), ("stats_dev", ctypes.c_void_p)]
+
+
+class mgp_batch_config(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("d", ctypes.c_int32), ("partition_bytes", ctypes.c_uint32),
+                ("b_max", ctypes.c_uint32), ("block_threads", ctypes.c_int32),
+                ("particles_per_thread", ctypes.c_int32), ("schedule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+class mgp_batch_info(ctypes.Structure):
+    _fields_ = [("filters", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("particles_per_thread", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("xcds", ctypes.c_int32), ("particles", ctypes.c_int64),
+                ("tiles", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("est_particle_steps", ctypes.c_double)]
+
+
 STATS_BYTES = ctypes.sizeof(mgp_stats)
 STATS_DTYPE = np.dtype([("w_sum", "<f8"), ("ratio", "<f8"), ("b_raw", "<f8"), ("w_max", "<f4"), ("B", "<u4"),
                         ("clamped", "<u4"), ("status", "<i4"), ("n", "<u4"), ("tag", "<u4")])
@@ -62,6 +83,16 @@ def lib():
         L.mgp_compute_B.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_resample_prepared.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_gather.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+        L.mgp_batch_plan_create.argtypes = [ctypes.POINTER(mgp_filter_desc), ctypes.c_int32,
+                                            ctypes.POINTER(mgp_batch_config), _vp, ctypes.POINTER(_vp)]
+        L.mgp_batch_set_seeds.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64), _vp]
+        L.mgp_batch_run.argtypes = [_vp, _vp]
+        L.mgp_batch_run_separate.argtypes = [_vp, _vp]
+        L.mgp_batch_plan_info.argtypes = [_vp, ctypes.POINTER(mgp_batch_info)]
+        L.mgp_batch_plan_destroy.argtypes = [_vp]
+        for f in ("mgp_batch_plan_create", "mgp_batch_set_seeds", "mgp_batch_run", "mgp_batch_run_separate",
+                  "mgp_batch_plan_info", "mgp_batch_plan_destroy"):
+            getattr(L, f).restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
         L.mgp_version.argtypes = []
@@ -124,6 +155,37 @@ def mgp_resample_prepared(w_dev: int, n: int, params: mgp_params, ancestors_dev:
 def mgp_gather(states_dev: int, n_states: int, d: int, ancestors_dev: int, n_out: int, out_dev: int,
                stream: int) -> None:
     _check(lib().mgp_gather(states_dev, n_states, d, ancestors_dev, n_out, out_dev, stream or None), "mgp_gather")
+
+
+def mgp_batch_plan_create(filters, config: mgp_batch_config, stream: int) -> int:
+    arr = (mgp_filter_desc * len(filters))(*filters)
+    plan = _vp()
+    _check(lib().mgp_batch_plan_create(arr, len(filters), ctypes.byref(config), stream or None, ctypes.byref(plan)),
+           "mgp_batch_plan_create")
+    return plan.value
+
+
+def mgp_batch_set_seeds(plan: int, seeds, stream: int) -> None:
+    arr = (ctypes.c_uint64 * len(seeds))(*[int(x) & (2**64 - 1) for x in seeds])
+    _check(lib().mgp_batch_set_seeds(plan, arr, stream or None), "mgp_batch_set_seeds")
+
+
+def mgp_batch_run(plan: int, stream: int) -> None:
+    _check(lib().mgp_batch_run(plan, stream or None), "mgp_batch_run")
+
+
+def mgp_batch_run_separate(plan: int, stream: int) -> None:
+    _check(lib().mgp_batch_run_separate(plan, stream or None), "mgp_batch_run_separate")
+
+
+def mgp_batch_plan_info(plan: int) -> dict:
+    info = mgp_batch_info()
+    _check(lib().mgp_batch_plan_info(plan, ctypes.byref(info)), "mgp_batch_plan_info")
+    return {k: getattr(info, k) for k, _ in mgp_batch_info._fields_}
+
+
+def mgp_batch_plan_destroy(plan: int) -> None:
+    _check(lib().mgp_batch_plan_destroy(plan), "mgp_batch_plan_destroy")
 
 
 # ---------------------------------------------------------------------------
@@ -211,3 +273,53 @@ def gather(states, anc, out=None, stream: int | None = None):
     mgp_gather(st2.data_ptr(), n_states, d, anc.data_ptr(), n_out, out.data_ptr(),
                current_stream() if stream is None else stream)
     return out
+
+
+class BatchPlan:
+    """Owns an mgp_batch_plan over device tensors.
+
+    filters: list of dicts with keys w (device fp32 [n]), anc (device int32
+    [n]), and optionally B, epsilon, seed, stream_id, states ([n, d]) and out
+    ([n, d]). The tensors must stay alive as long as the plan."""
+
+    def __init__(self, filters, variant="megopolis", d: int = 0, partition_bytes: int = 128, b_max: int = 0,
+                 block_threads: int = 0, particles_per_thread: int = 0, schedule: int = 0, use_graph: bool = True,
+                 tune_cache: str | None = None, stream: int | None = None):
+        self.filters = filters
+        descs = []
+        for f in filters:
+            st = f.get("states")
+            descs.append(mgp_filter_desc(f["w"].data_ptr(), f["w"].numel(), int(f.get("B", 0)),
+                                         float(f.get("epsilon", 0.01)), int(f.get("seed", 0)) & (2**64 - 1),
+                                         int(f.get("stream_id", 0)), 0, f["anc"].data_ptr(),
+                                         st.data_ptr() if st is not None else None,
+                                         f["out"].data_ptr() if st is not None else None,
+                                         f["stats"].data_ptr() if f.get("stats") is not None else None))
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self._cache = tune_cache.encode() if tune_cache else None
+        cfg = mgp_batch_config(v, int(d), int(partition_bytes), int(b_max), int(block_threads),
+                               int(particles_per_thread), int(schedule), 1 if use_graph else 0, self._cache)
+        self.plan = mgp_batch_plan_create(descs, cfg, current_stream() if stream is None else stream)
+
+    def info(self) -> dict:
+        return mgp_batch_plan_info(self.plan)
+
+    def set_seeds(self, seeds, stream: int | None = None) -> None:
+        mgp_batch_set_seeds(self.plan, seeds, current_stream() if stream is None else stream)
+
+    def run(self, stream: int | None = None) -> None:
+        mgp_batch_run(self.plan, current_stream() if stream is None else stream)
+
+    def run_separate(self, stream: int | None = None) -> None:
+        mgp_batch_run_separate(self.plan, current_stream() if stream is None else stream)
+
+    def close(self) -> None:
+        if self.plan:
+            mgp_batch_plan_destroy(self.plan)
+            self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

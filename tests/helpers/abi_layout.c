@@ -1,0 +1,31 @@
+/* Prints sizeof / offsetof of the C ABI structs of include/mgp.h, so the
+ * test-suite can check the Python binding's ctypes mirrors against them. */
+#include <stddef.h>
+#include <stdio.h>
+
+#include "mgp.h"
+
+#define F(T, m) printf("\"%s.%s\": %zu,\n", #T, #m, offsetof(T, m))
+#define S(T) printf("\"%s\": %zu,\n", #T, sizeof(T))
+
+int main(void)
+{
+    printf("{\n");
+    S(mgp_params); F(mgp_params, variant); F(mgp_params, B); F(mgp_params, epsilon); F(mgp_params, seed);
+    F(mgp_params, stream_id); F(mgp_params, partition_bytes); F(mgp_params, b_max); F(mgp_params, reserved);
+    S(mgp_stats); F(mgp_stats, w_sum); F(mgp_stats, ratio); F(mgp_stats, b_raw); F(mgp_stats, w_max); F(mgp_stats, B);
+    F(mgp_stats, clamped); F(mgp_stats, status); F(mgp_stats, n); F(mgp_stats, tag);
+    S(mgp_filter_desc); F(mgp_filter_desc, w_dev); F(mgp_filter_desc, n); F(mgp_filter_desc, B);
+    F(mgp_filter_desc, epsilon); F(mgp_filter_desc, seed); F(mgp_filter_desc, stream_id); F(mgp_filter_desc, reserved);
+    F(mgp_filter_desc, ancestors_dev); F(mgp_filter_desc, states_dev); F(mgp_filter_desc, out_states_dev);
+    F(mgp_filter_desc, stats_dev);
+    S(mgp_batch_config); F(mgp_batch_config, variant); F(mgp_batch_config, d); F(mgp_batch_config, partition_bytes);
+    F(mgp_batch_config, b_max); F(mgp_batch_config, block_threads); F(mgp_batch_config, particles_per_thread);
+    F(mgp_batch_config, schedule); F(mgp_batch_config, use_graph); F(mgp_batch_config, tune_cache);
+    S(mgp_batch_info); F(mgp_batch_info, filters); F(mgp_batch_info, block_threads);
+    F(mgp_batch_info, particles_per_thread); F(mgp_batch_info, schedule); F(mgp_batch_info, from_cache);
+    F(mgp_batch_info, xcds); F(mgp_batch_info, particles); F(mgp_batch_info, tiles); F(mgp_batch_info, device_bytes);
+    F(mgp_batch_info, est_particle_steps);
+    printf("\"end\": 0\n}\n");
+    return 0;
+}

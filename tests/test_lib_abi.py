@@ -46,9 +46,19 @@ def test_library_exports_every_declared_symbol(mgp):
         assert hasattr(lib, f)
 
 
-def test_struct_layouts_match_header(mgp):
-    assert ctypes.sizeof(mgp.mgp_params) == 40
-    assert ctypes.sizeof(mgp.mgp_stats) == 48
+def test_struct_layouts_match_header(mgp, tmp_path):
+    """sizeof / offsetof of every ABI struct, from a C program built against
+    include/mgp.h, equal the ctypes mirrors in the binding."""
+    import json
+    exe = tmp_path / "abi_layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    os.path.join(ROOT, "tests", "helpers", "abi_layout.c")], check=True)
+    layout = json.loads(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
+    for name in ("mgp_params", "mgp_stats", "mgp_filter_desc", "mgp_batch_config", "mgp_batch_info"):
+        cls = getattr(mgp, name)
+        assert ctypes.sizeof(cls) == layout[name], name
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == layout[f"{name}.{field}"], (name, field)
 
 
 def test_workspace_size_host_only(mgp):
