@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=16, help="oracle runs every k-th particle's chain")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-filters section")
     ap.add_argument("--batch-runs", type=int, default=20)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
     return ap.parse_args()
@@ -185,6 +187,73 @@ def batched_section(torch, mgp, inputs, runs):
     }
 
 
+def serving_section(torch, mgp, inputs, n_requests):
+    """Poisson stream of requests, N = round(2^U(12, 22)), y ~ U[0, 4], D = 16
+    states resident on the device, Megopolis, admitted by HBM budget. The
+    arrival rate is 70% of the capacity measured with all requests queued at
+    once; a second run with a 2 GB budget forces queueing."""
+    import threading
+
+    import numpy as np
+    dev = torch.device("cuda:0")
+    sets = 48
+    g = np.random.Generator(np.random.PCG64(inputs.SERVE_SEED))
+    sizes = np.rint(2.0 ** g.uniform(12.0, 22.0, sets)).astype(int)
+    ys = g.uniform(0.0, 4.0, sets)
+    pool = []
+    for k, (n, y) in enumerate(zip(sizes, ys)):
+        w, st = inputs.gaussian_weights_and_states(int(n), float(y), 16, 3000 + k)
+        pool.append((torch.from_numpy(w).to(dev), torch.from_numpy(st).to(dev)))
+    torch.cuda.synchronize()
+
+    def run(budget, rate, count, open_loop=True):
+        srv = mgp.Server("megopolis", d=16, hbm_budget=budget, streams=4, max_batch=32)
+        arrivals = np.cumsum(np.random.Generator(np.random.PCG64(7)).exponential(1.0 / rate, count)) if open_loop \
+            else np.zeros(count)
+        tickets = [None] * count
+        ready = threading.Semaphore(0)
+
+        def submitter():
+            t0 = time.perf_counter()
+            for k in range(count):
+                while time.perf_counter() - t0 < arrivals[k]:
+                    pass
+                w, st = pool[k % sets]
+                tickets[k] = srv.submit(w, seed=10_000 + k, stream_id=k, states=st)
+                ready.release()
+
+        th = threading.Thread(target=submitter)
+        w0 = time.perf_counter()
+        th.start()
+        lat, parts = [], 0
+        for k in range(count):
+            ready.acquire()
+            r = srv.wait(tickets[k], 120000.0)
+            assert r["state"] == 2
+            lat.append((r["t_done"] - r["t_submit"]) * 1000.0)
+            parts += r["n"]
+            srv.release(tickets[k])
+        th.join()
+        wall = time.perf_counter() - w0
+        st = srv.stats()
+        srv.close()
+        return {"requests": count, "wall_s": wall, "particles_per_s": parts / wall,
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)),
+                "micro_batches": st["micro_batches"], "pool_peak_bytes": st["pool_peak"],
+                "max_concurrent_batches": st["max_concurrent_batches"]}
+
+    cap = run(16 << 30, 1.0, 400, open_loop=False)
+    mean_n = float(np.mean(sizes))
+    capacity_rps = cap["particles_per_s"] / mean_n
+    rate = 0.7 * capacity_rps
+    main_run = run(16 << 30, rate, n_requests)
+    tight = run(2 << 30, rate, max(500, n_requests // 4))
+    return {"workload": "Poisson requests, N=round(2^U(12,22)), y~U[0,4], D=16 states resident, Megopolis, "
+                        "4 streams, micro-batches <= 32",
+            "capacity_particles_per_s": cap["particles_per_s"], "capacity_requests_per_s": capacity_rps,
+            "arrival_rate_per_s": rate, "budget_16GB": main_run, "budget_2GB": tight}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +353,13 @@ def main():
         bt = result["batched"]
         log(f"[bench] batched: graph {bt['graph_ms']:.3f} ms/run, separate {bt['separate_ms']:.3f} ms/run "
             f"-> {bt['speedup_vs_separate']:.2f}x, shape {bt['tuned_shape']}")
+
+    if not args.no_serving:
+        log("[bench] serving")
+        result["serving"] = serving_section(torch, mgp, inputs, args.serve_requests)
+        sv = result["serving"]["budget_16GB"]
+        log(f"[bench] serving: p50 {sv['p50_ms']:.3f} ms, p99 {sv['p99_ms']:.3f} ms, "
+            f"{sv['particles_per_s']:.3e} particles/s")
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

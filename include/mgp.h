@@ -197,6 +197,96 @@ int mgp_batch_plan_info(const mgp_batch_plan* plan, mgp_batch_info* info);
 /* Frees the plan's device memory and graph. The plan must be idle. */
 int mgp_batch_plan_destroy(mgp_batch_plan* plan);
 
+/* ---- serving ------------------------------------------------------------
+ * A resample server: requests of mixed size arrive at any time, are
+ * admitted while earlier ones run, and are executed in micro-batches on
+ * several HIP streams (continuous batching). Inputs (weights, states) stay
+ * where the caller keeps them in device memory; the server allocates every
+ * request's outputs and workspace from one device pool of hbm_budget bytes,
+ * so admission is exactly "the request's footprint fits the pool now".
+ * Requests are admitted in arrival order. A request's result is a pure
+ * function of its own (weights, B / epsilon, seed, stream_id): identical
+ * alone and in any mix. */
+typedef struct mgp_server_config {
+    int32_t variant;             /* mgp_variant of every request */
+    int32_t d;                   /* state dimension of the fused gather (0: none) */
+    uint32_t partition_bytes;    /* C1/C2; 0 means 128 */
+    uint32_t b_max;              /* per-request clamp / limit of B; 0 means 65536 */
+    uint64_t hbm_budget;         /* bytes of the device pool for outputs + workspaces */
+    int32_t streams;             /* HIP streams running micro-batches concurrently (>= 1) */
+    int32_t max_batch;           /* requests per micro-batch (>= 1) */
+    int64_t max_batch_particles; /* particles per micro-batch; 0 means 2^24 */
+    int32_t max_n;               /* largest request size accepted; 0 means 2^22 */
+    int32_t simulate;            /* 1: no device work; completions are simulated (host tests) */
+    double sim_us_fixed;         /* simulated executor: time per micro-batch, microseconds */
+    double sim_ns_per_particle;  /* simulated executor: time per particle of a micro-batch */
+    int32_t sim_fail_every;      /* simulated executor: fail every k-th micro-batch (0: never) */
+    int32_t reserved;
+} mgp_server_config;
+
+typedef struct mgp_request {
+    const float* w_dev;          /* n fp32 weights (device), kept valid until the request completes */
+    int32_t n;
+    uint32_t B;                  /* > 0: iterations; 0: from epsilon */
+    double epsilon;
+    uint64_t seed;
+    uint32_t stream_id;
+    uint32_t reserved;           /* must be 0 */
+    const float* states_dev;     /* n x d fp32 (device), or NULL for ancestors only */
+} mgp_request;
+
+enum { MGP_REQ_QUEUED = 0, MGP_REQ_RUNNING = 1, MGP_REQ_DONE = 2, MGP_REQ_FAILED = 3, MGP_REQ_CANCELLED = 4 };
+
+typedef struct mgp_request_result {
+    int32_t state;               /* MGP_REQ_* */
+    int32_t status;              /* mgp_stats.status of the request (MGP_EWEIGHTS for invalid weights) */
+    uint32_t B;                  /* iterations used */
+    int32_t n;
+    const int32_t* ancestors_dev;/* server-owned, valid until mgp_server_release */
+    const float* out_states_dev; /* server-owned (NULL without states), valid until mgp_server_release */
+    double t_submit, t_admit, t_dispatch, t_done; /* seconds since the server started */
+} mgp_request_result;
+
+typedef struct mgp_server_stats {
+    int64_t submitted, admitted, completed, failed, cancelled, released;
+    int64_t micro_batches;
+    int64_t queued;              /* waiting for admission now */
+    int64_t in_flight;           /* admitted, not completed */
+    uint64_t pool_bytes;         /* size of the device pool */
+    uint64_t pool_in_use;        /* bytes allocated now */
+    uint64_t pool_peak;          /* high-water mark of pool_in_use */
+    int64_t max_concurrent_batches; /* most micro-batches on the device at once */
+} mgp_server_stats;
+
+typedef struct mgp_server mgp_server;
+
+/* Starts the server: allocates the pool and per-stream tables, starts the
+ * scheduler thread. */
+int mgp_server_create(const mgp_server_config* config, mgp_server** server);
+
+/* Queues a request (thread-safe, non-blocking). MGP_ENOMEM if its footprint
+ * can never fit the pool; MGP_EINVAL / MGP_ERANGE for bad arguments. */
+int mgp_server_submit(mgp_server* server, const mgp_request* request, uint64_t* ticket);
+
+/* Current state of a request (thread-safe). */
+int mgp_server_poll(mgp_server* server, uint64_t ticket, mgp_request_result* result);
+
+/* Waits until the request is done, failed or cancelled, or timeout_ms passes
+ * (MGP_EBUSY then; a negative timeout waits forever). */
+int mgp_server_wait(mgp_server* server, uint64_t ticket, double timeout_ms, mgp_request_result* result);
+
+/* Cancels a request that is still queued; MGP_EBUSY once it was admitted. */
+int mgp_server_cancel(mgp_server* server, uint64_t ticket);
+
+/* Returns a finished request's outputs to the pool and forgets the ticket. */
+int mgp_server_release(mgp_server* server, uint64_t ticket);
+
+int mgp_server_get_stats(mgp_server* server, mgp_server_stats* stats);
+
+/* Stops accepting requests, cancels those still queued, lets admitted ones
+ * finish, frees everything. Outputs not yet released become invalid. */
+int mgp_server_destroy(mgp_server* server);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* mgp_last_error(void);
 

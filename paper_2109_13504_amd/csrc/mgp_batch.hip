@@ -36,44 +36,9 @@
 #include "mgp_device.h"
 #include "mgp_internal.h"
 #include "mgp_reduce.h"
+#include "mgp_batch_internal.h"
 
 namespace mgp {
-
-constexpr uint32_t kNoFilter = 0xFFFFFFFFu;
-constexpr uint32_t kBatchMaxN = kMirrorMaxN;
-constexpr int kMaxXcd = 8;
-
-// Per-filter record in device memory (read with scalar loads).
-struct FilterDev {
-    const float* w;
-    int32_t* anc;
-    const float* states;
-    float* out;
-    mgp_stats* stats_user;
-    float* mirror;       // Megopolis: 2n + kMirrorPad floats, else null
-    uint32_t* offsets;   // Megopolis: b_max entries, else null
-    double eps;
-    uint32_t n;
-    uint32_t B_user;
-    uint32_t b_max;
-    uint32_t key0, key1;
-    uint32_t stream_id;
-    uint32_t part_base;  // first partial of this filter
-    uint32_t nparts;
-    uint32_t chunk;
-    uint32_t n_w, n_part;
-    uint32_t vec;        // the reduction may use float4 loads
-    uint32_t rows4;      // the gather may use float4 rows
-    uint32_t pad[3];
-};
-
-struct RTile {
-    uint32_t f, c;
-};
-
-struct LTile {
-    uint32_t f, start;
-};
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -232,10 +197,6 @@ __global__ __launch_bounds__(BT) void k_batch_loop_persistent(const FilterDev* _
 // ---------------------------------------------------------------------------
 // Launch table
 // ---------------------------------------------------------------------------
-struct LoopShape {
-    int bt, ppt, sched;
-};
-
 struct LoopArgs {
     const FilterDev* fd;
     const mgp_stats* stats;
@@ -344,11 +305,69 @@ static std::vector<LoopShape> candidate_shapes(int variant)
     return c;
 }
 
-static bool shape_supported(int variant, const LoopShape& sh)
+bool batch_shape_supported(int variant, const LoopShape& sh)
 {
     for (const LoopShape& c : candidate_shapes(variant))
         if (c.bt == sh.bt && c.ppt == sh.ppt && c.sched == sh.sched) return true;
     return false;
+}
+
+void build_tile_table(const std::vector<uint32_t>& n, const std::vector<double>& cost, const LoopShape& sh, int nx,
+                      std::vector<LTile>& table, uint32_t* qoff)
+{
+    const uint32_t tile = (uint32_t)(sh.bt * sh.ppt);
+    const int count = (int)n.size();
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(nx, 0.0);
+    std::vector<std::vector<int>> per(nx);
+    for (int f : order) {
+        int best = 0;
+        for (int x = 1; x < nx; ++x)
+            if (load[x] < load[best]) best = x;
+        load[best] += cost[f];
+        per[best].push_back(f);
+    }
+    std::vector<std::vector<LTile>> lists(nx);
+    for (int x = 0; x < nx; ++x) {
+        // costlier tiles (larger cost per particle) first inside the XCD
+        std::stable_sort(per[x].begin(), per[x].end(),
+                         [&](int a, int b) { return cost[a] / n[a] > cost[b] / n[b]; });
+        for (int f : per[x])
+            for (uint32_t st = 0; st < n[f]; st += tile) lists[x].push_back(LTile{(uint32_t)f, st});
+    }
+    table.clear();
+    for (int x = 0; x <= kMaxXcd; ++x) qoff[x] = 0;
+    if (sh.sched == 1) {
+        size_t mx = 0;
+        for (auto& l : lists) mx = std::max(mx, l.size());
+        table.assign(mx * nx, LTile{kNoFilter, 0});
+        for (int x = 0; x < nx; ++x)
+            for (size_t m = 0; m < lists[x].size(); ++m) table[m * nx + x] = lists[x][m];
+    } else {
+        for (int x = 0; x < nx; ++x) {
+            qoff[x] = (uint32_t)table.size();
+            table.insert(table.end(), lists[x].begin(), lists[x].end());
+        }
+        qoff[nx] = (uint32_t)table.size();
+    }
+}
+
+int enqueue_batch(int variant, const LoopShape& sh, const FilterDev* d_fd, uint32_t count, const RTile* d_rt,
+                  uint32_t n_rt, Partial* d_parts, mgp_stats* d_stats, const LTile* d_lt, uint32_t grid,
+                  const uint32_t* d_qoff, uint32_t* d_qcount, uint32_t nxcd, uint32_t d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reduce, dim3(n_rt), dim3(kReduceThreads), 0, s, d_fd, d_rt, d_parts);
+    int rc = check_launch("batch reduce");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(kReduceThreads), 0, s, d_fd, d_parts, d_stats, d_qcount,
+                       (uint32_t)kMaxXcd);
+    rc = check_launch("batch finalize");
+    if (rc) return rc;
+    LoopArgs a{d_fd, d_stats, d_lt, d_qoff, d_qcount, nxcd, d, grid};
+    if (!launch_loop(variant, sh, a, s)) return fail(MGP_EINVAL, "unsupported launch shape bt=%d ppt=%d", sh.bt, sh.ppt);
+    return check_launch("batch accept loop");
 }
 
 }  // namespace mgp
@@ -472,44 +491,19 @@ void write_cache(const std::string& path, const std::map<std::string, LoopShape>
 // XCDs by LPT on N_f * B_f, tiles of heavier filters first inside each XCD.
 int build_tiles(mgp_batch_plan* p, const LoopShape& sh, hipStream_t s)
 {
-    const uint32_t tile = (uint32_t)(sh.bt * sh.ppt);
     const int nx = p->nxcd;
-    std::vector<int> order(p->count);
-    for (int i = 0; i < p->count; ++i) order[i] = i;
-    auto cost = [&](int f) { return (double)p->filters[f].n * std::max<uint32_t>(1u, p->est_B[f]); };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    std::vector<double> load(nx, 0.0);
-    std::vector<std::vector<int>> per(nx);
-    for (int f : order) {
-        int best = 0;
-        for (int x = 1; x < nx; ++x)
-            if (load[x] < load[best]) best = x;
-        load[best] += cost(f);
-        per[best].push_back(f);
-    }
-    std::vector<std::vector<LTile>> lists(nx);
-    for (int x = 0; x < nx; ++x) {
-        // heavier tiles (larger B) first inside the XCD
-        std::stable_sort(per[x].begin(), per[x].end(),
-                         [&](int a, int b) { return p->est_B[a] > p->est_B[b]; });
-        for (int f : per[x])
-            for (uint32_t st = 0; st < (uint32_t)p->filters[f].n; st += tile) lists[x].push_back(LTile{(uint32_t)f, st});
+    std::vector<uint32_t> ns(p->count);
+    std::vector<double> cost(p->count);
+    for (int f = 0; f < p->count; ++f) {
+        ns[f] = (uint32_t)p->filters[f].n;
+        cost[f] = (double)ns[f] * std::max<uint32_t>(1u, p->est_B[f]);
     }
     std::vector<LTile> table;
     std::vector<uint32_t> qoff(kMaxXcd + 1, 0);
+    build_tile_table(ns, cost, sh, nx, table, qoff.data());
     if (sh.sched == 1) {
-        size_t mx = 0;
-        for (auto& l : lists) mx = std::max(mx, l.size());
-        table.assign(mx * nx, LTile{kNoFilter, 0});
-        for (int x = 0; x < nx; ++x)
-            for (size_t m = 0; m < lists[x].size(); ++m) table[m * nx + x] = lists[x][m];
         p->grid = (uint32_t)table.size();
     } else {
-        for (int x = 0; x < nx; ++x) {
-            qoff[x] = (uint32_t)table.size();
-            table.insert(table.end(), lists[x].begin(), lists[x].end());
-        }
-        qoff[nx] = (uint32_t)table.size();
         // resident blocks per CU of the persistent kernel decide its grid
         const int occ = persistent_occupancy(p->variant, sh);
         uint32_t g = (uint32_t)(p->cu_count * occ);
@@ -535,17 +529,8 @@ int build_tiles(mgp_batch_plan* p, const LoopShape& sh, hipStream_t s)
 
 int enqueue_run(mgp_batch_plan* p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_reduce, dim3(p->n_rtiles), dim3(kReduceThreads), 0, s, p->d_fd, p->d_rtiles, p->d_parts);
-    int rc = check_launch("batch reduce");
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_batch_finalize, dim3(p->count), dim3(kReduceThreads), 0, s, p->d_fd, p->d_parts, p->d_stats,
-                       p->d_qcount, (uint32_t)kMaxXcd);
-    rc = check_launch("batch finalize");
-    if (rc) return rc;
-    LoopArgs a{p->d_fd, p->d_stats, p->d_ltiles, p->d_qoff, p->d_qcount, (uint32_t)p->nxcd, p->d, p->grid};
-    if (!launch_loop(p->variant, p->shape, a, s))
-        return fail(MGP_EINVAL, "unsupported launch shape bt=%d ppt=%d", p->shape.bt, p->shape.ppt);
-    return check_launch("batch accept loop");
+    return enqueue_batch(p->variant, p->shape, p->d_fd, (uint32_t)p->count, p->d_rtiles, p->n_rtiles, p->d_parts,
+                         p->d_stats, p->d_ltiles, p->grid, p->d_qoff, p->d_qcount, (uint32_t)p->nxcd, p->d, s);
 }
 
 int capture_graph(mgp_batch_plan* p)
@@ -624,7 +609,7 @@ int mgp_batch_plan_create(const mgp_filter_desc* filters, int32_t count, const m
                              cfg->particles_per_thread ? cfg->particles_per_thread
                                                        : (cfg->variant == MGP_MEGOPOLIS ? 4 : 1),
                              cfg->schedule ? cfg->schedule : 1};
-        if (!shape_supported(cfg->variant, want))
+        if (!batch_shape_supported(cfg->variant, want))
             return fail(MGP_EINVAL, "unsupported launch shape bt=%d ppt=%d schedule=%d", want.bt, want.ppt, want.sched);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -764,7 +749,7 @@ int mgp_batch_plan_create(const mgp_filter_desc* filters, int32_t count, const m
         std::map<std::string, LoopShape> cache;
         if (!p->tune_cache.empty()) cache = read_cache(p->tune_cache);
         auto it = cache.find(key);
-        if (it != cache.end() && shape_supported(p->variant, it->second)) {
+        if (it != cache.end() && batch_shape_supported(p->variant, it->second)) {
             chosen = it->second;
             p->from_cache = 1;
         } else {

@@ -60,6 +60,38 @@ class mgp_batch_info(ctypes.Structure):
                 ("tiles", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("est_particle_steps", ctypes.c_double)]
 
 
+class mgp_server_config(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("d", ctypes.c_int32), ("partition_bytes", ctypes.c_uint32),
+                ("b_max", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_batch_particles", ctypes.c_int64), ("max_n", ctypes.c_int32),
+                ("simulate", ctypes.c_int32), ("sim_us_fixed", ctypes.c_double),
+                ("sim_ns_per_particle", ctypes.c_double), ("sim_fail_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class mgp_request(ctypes.Structure):
+    _fields_ = [("w_dev", ctypes.c_void_p), ("n", ctypes.c_int32), ("B", ctypes.c_uint32),
+                ("epsilon", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("states_dev", ctypes.c_void_p)]
+
+
+class mgp_request_result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("B", ctypes.c_uint32), ("n", ctypes.c_int32),
+                ("ancestors_dev", ctypes.c_void_p), ("out_states_dev", ctypes.c_void_p),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_dispatch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class mgp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64), ("released", ctypes.c_int64),
+                ("micro_batches", ctypes.c_int64), ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_uint64), ("pool_in_use", ctypes.c_uint64), ("pool_peak", ctypes.c_uint64),
+                ("max_concurrent_batches", ctypes.c_int64)]
+
+
+MGP_REQ_QUEUED, MGP_REQ_RUNNING, MGP_REQ_DONE, MGP_REQ_FAILED, MGP_REQ_CANCELLED = 0, 1, 2, 3, 4
+
 STATS_BYTES = ctypes.sizeof(mgp_stats)
 STATS_DTYPE = np.dtype([("w_sum", "<f8"), ("ratio", "<f8"), ("b_raw", "<f8"), ("w_max", "<f4"), ("B", "<u4"),
                         ("clamped", "<u4"), ("status", "<i4"), ("n", "<u4"), ("tag", "<u4")])
@@ -92,6 +124,17 @@ def lib():
         L.mgp_batch_plan_destroy.argtypes = [_vp]
         for f in ("mgp_batch_plan_create", "mgp_batch_set_seeds", "mgp_batch_run", "mgp_batch_run_separate",
                   "mgp_batch_plan_info", "mgp_batch_plan_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        L.mgp_server_create.argtypes = [ctypes.POINTER(mgp_server_config), ctypes.POINTER(_vp)]
+        L.mgp_server_submit.argtypes = [_vp, ctypes.POINTER(mgp_request), ctypes.POINTER(ctypes.c_uint64)]
+        L.mgp_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(mgp_request_result)]
+        L.mgp_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(mgp_request_result)]
+        L.mgp_server_cancel.argtypes = [_vp, ctypes.c_uint64]
+        L.mgp_server_release.argtypes = [_vp, ctypes.c_uint64]
+        L.mgp_server_get_stats.argtypes = [_vp, ctypes.POINTER(mgp_server_stats)]
+        L.mgp_server_destroy.argtypes = [_vp]
+        for f in ("mgp_server_create", "mgp_server_submit", "mgp_server_poll", "mgp_server_wait", "mgp_server_cancel",
+                  "mgp_server_release", "mgp_server_get_stats", "mgp_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
@@ -186,6 +229,52 @@ def mgp_batch_plan_info(plan: int) -> dict:
 
 def mgp_batch_plan_destroy(plan: int) -> None:
     _check(lib().mgp_batch_plan_destroy(plan), "mgp_batch_plan_destroy")
+
+
+def mgp_server_create(config: mgp_server_config) -> int:
+    h = _vp()
+    _check(lib().mgp_server_create(ctypes.byref(config), ctypes.byref(h)), "mgp_server_create")
+    return h.value
+
+
+def mgp_server_submit(server: int, request: mgp_request) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().mgp_server_submit(server, ctypes.byref(request), ctypes.byref(t)), "mgp_server_submit")
+    return t.value
+
+
+def _result_dict(r: mgp_request_result) -> dict:
+    return {k: getattr(r, k) for k, _ in mgp_request_result._fields_}
+
+
+def mgp_server_poll(server: int, ticket: int) -> dict:
+    r = mgp_request_result()
+    _check(lib().mgp_server_poll(server, ticket, ctypes.byref(r)), "mgp_server_poll")
+    return _result_dict(r)
+
+
+def mgp_server_wait(server: int, ticket: int, timeout_ms: float = -1.0) -> dict:
+    r = mgp_request_result()
+    _check(lib().mgp_server_wait(server, ticket, timeout_ms, ctypes.byref(r)), "mgp_server_wait")
+    return _result_dict(r)
+
+
+def mgp_server_cancel(server: int, ticket: int) -> None:
+    _check(lib().mgp_server_cancel(server, ticket), "mgp_server_cancel")
+
+
+def mgp_server_release(server: int, ticket: int) -> None:
+    _check(lib().mgp_server_release(server, ticket), "mgp_server_release")
+
+
+def mgp_server_get_stats(server: int) -> dict:
+    st = mgp_server_stats()
+    _check(lib().mgp_server_get_stats(server, ctypes.byref(st)), "mgp_server_get_stats")
+    return {k: getattr(st, k) for k, _ in mgp_server_stats._fields_}
+
+
+def mgp_server_destroy(server: int) -> None:
+    _check(lib().mgp_server_destroy(server), "mgp_server_destroy")
 
 
 # ---------------------------------------------------------------------------
@@ -323,3 +412,87 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """A resample server (mgp_server_*). Requests name device tensors (or raw
+    device addresses) for weights and states; outputs are owned by the
+    server until release()."""
+
+    def __init__(self, variant="megopolis", d: int = 0, hbm_budget: int = 16 << 30, streams: int = 4,
+                 max_batch: int = 64, max_batch_particles: int = 0, max_n: int = 0, b_max: int = 0,
+                 partition_bytes: int = 128, simulate: bool = False, sim_us_fixed: float = 0.0,
+                 sim_ns_per_particle: float = 0.0, sim_fail_every: int = 0):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        cfg = mgp_server_config(v, int(d), int(partition_bytes), int(b_max), int(hbm_budget), int(streams),
+                                int(max_batch), int(max_batch_particles), int(max_n), 1 if simulate else 0,
+                                float(sim_us_fixed), float(sim_ns_per_particle), int(sim_fail_every), 0)
+        self.handle = mgp_server_create(cfg)
+        self.d = d
+
+    def submit(self, w, n: int | None = None, B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
+               states=None) -> int:
+        wp = w if isinstance(w, int) else w.data_ptr()
+        n = n if n is not None else w.numel()
+        sp = None if states is None else (states if isinstance(states, int) else states.data_ptr())
+        req = mgp_request(wp, int(n), int(B), float(epsilon), int(seed) & (2**64 - 1), int(stream_id), 0, sp)
+        return mgp_server_submit(self.handle, req)
+
+    def poll(self, ticket: int) -> dict:
+        return mgp_server_poll(self.handle, ticket)
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> dict:
+        return mgp_server_wait(self.handle, ticket, timeout_ms)
+
+    def cancel(self, ticket: int) -> None:
+        mgp_server_cancel(self.handle, ticket)
+
+    def release(self, ticket: int) -> None:
+        mgp_server_release(self.handle, ticket)
+
+    def stats(self) -> dict:
+        return mgp_server_get_stats(self.handle)
+
+    def outputs(self, result: dict):
+        """Copies a finished request's ancestors (and gathered states) to host numpy arrays."""
+        torch = _torch()
+        n = result["n"]
+        anc = torch.empty(n, dtype=torch.int32, device="cuda")
+        _hip_copy(anc.data_ptr(), result["ancestors_dev"], 4 * n)
+        out = None
+        if result["out_states_dev"]:
+            out = torch.empty((n, self.d), dtype=torch.float32, device="cuda")
+            _hip_copy(out.data_ptr(), result["out_states_dev"], 4 * n * self.d)
+        torch.cuda.synchronize()
+        return anc.cpu().numpy(), (out.cpu().numpy() if out is not None else None)
+
+    def close(self) -> None:
+        if self.handle:
+            mgp_server_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _hip_copy(dst: int, src: int, nbytes: int) -> None:
+    """Device-to-device copy between raw device addresses on torch's current stream."""
+    rc = _copy_lib().hipMemcpyDtoDAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes),
+                                        ctypes.c_void_p(current_stream()))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyDtoDAsync failed ({rc})")
+
+
+_hip = None
+
+
+def _copy_lib():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyDtoDAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        _hip.hipMemcpyDtoDAsync.restype = ctypes.c_int
+    return _hip

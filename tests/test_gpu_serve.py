@@ -1,0 +1,133 @@
+"""Serving on the GPU: each request's ancestors and gathered states are the
+same when it runs alone and when it runs in a mix of concurrent requests,
+and equal the oracle; a tight HBM budget makes requests queue but all
+complete within the budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_13504_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2109_13504_amd import mgp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mgp.lib()
+    return torch, torch.device("cuda:0"), mgp
+
+
+def request_set(torch, dev, count, d, seed=3, lo=10.0, hi=18.0):
+    g = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.rint(2.0 ** g.uniform(lo, hi, count)).astype(int)
+    ys = g.uniform(0.0, 4.0, count)
+    reqs = []
+    for k, (n, y) in enumerate(zip(sizes, ys)):
+        w, st = inputs.gaussian_weights_and_states(int(n), float(y), d, 100 + k)
+        item = {"w": torch.from_numpy(w).to(dev), "w_np": w, "st_np": st, "seed": 5000 + k, "stream_id": k,
+                "states": torch.from_numpy(st).to(dev) if k % 4 != 3 else None}
+        reqs.append(item)
+    return reqs
+
+
+def run_alone(srv, reqs):
+    out = []
+    for r in reqs:
+        t = srv.submit(r["w"], seed=r["seed"], stream_id=r["stream_id"], states=r["states"])
+        res = srv.wait(t, 60000.0)
+        assert res["state"] == 2, res
+        out.append((res["B"], *srv.outputs(res)))
+        srv.release(t)
+    return out
+
+
+def run_mixed(srv, reqs):
+    """All requests from two client threads with jittered arrivals."""
+    tickets = [None] * len(reqs)
+
+    def client(part):
+        g = np.random.Generator(np.random.PCG64(part))
+        for k in range(part, len(reqs), 2):
+            r = reqs[k]
+            time.sleep(float(g.uniform(0, 0.0005)))
+            tickets[k] = srv.submit(r["w"], seed=r["seed"], stream_id=r["stream_id"], states=r["states"])
+
+    th = [threading.Thread(target=client, args=(p,)) for p in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    out = []
+    for t in tickets:
+        res = srv.wait(t, 60000.0)
+        assert res["state"] == 2, res
+        out.append((res["B"], *srv.outputs(res)))
+        srv.release(t)
+    return out
+
+
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis"])
+def test_alone_equals_mixed_equals_oracle(env, variant):
+    torch, dev, mgp = env
+    d = 16
+    reqs = request_set(torch, dev, 24, d)
+    srv = mgp.Server(variant, d=d, hbm_budget=4 << 30, streams=4, max_batch=8)
+    alone = run_alone(srv, reqs)
+    mixed = run_mixed(srv, reqs)
+    st = srv.stats()
+    assert st["completed"] == 48 and st["pool_in_use"] == 0
+    for k, r in enumerate(reqs):
+        assert alone[k][0] == mixed[k][0]
+        np.testing.assert_array_equal(alone[k][1], mixed[k][1], err_msg=f"request {k}")
+        if r["states"] is not None:
+            np.testing.assert_array_equal(alone[k][2], mixed[k][2])
+        else:
+            assert mixed[k][2] is None
+    for k in (0, 5, 11):
+        r = reqs[k]
+        ref = oracle.resample(r["w_np"], variant, alone[k][0], r["seed"], stream_id=r["stream_id"])
+        np.testing.assert_array_equal(alone[k][1], ref)
+        if r["states"] is not None:
+            np.testing.assert_array_equal(alone[k][2], oracle.gather(r["st_np"], ref))
+    srv.close()
+
+
+def test_tight_budget_queues_and_completes(env):
+    torch, dev, mgp = env
+    d = 16
+    reqs = request_set(torch, dev, 12, d, seed=9, lo=16.0, hi=18.0)
+    budget = 64 << 20  # a handful of requests at a time
+    srv = mgp.Server("megopolis", d=d, hbm_budget=budget, streams=4, max_batch=4)
+    mixed = run_mixed(srv, reqs)
+    st = srv.stats()
+    assert st["pool_peak"] <= budget and st["completed"] == 12
+    big = mgp.Server("megopolis", d=d, hbm_budget=4 << 30, streams=4, max_batch=8)
+    ref = run_alone(big, reqs)
+    for k in range(len(reqs)):
+        np.testing.assert_array_equal(mixed[k][1], ref[k][1])
+    srv.close()
+    big.close()
+
+
+def test_invalid_request_is_isolated(env):
+    torch, dev, mgp = env
+    srv = mgp.Server("megopolis", d=0, hbm_budget=1 << 30, streams=2, max_batch=4)
+    good = inputs.gaussian_weights(3000, 2.0, 1)
+    bad = good.copy()
+    bad[10] = np.nan
+    tg = srv.submit(torch.from_numpy(good).to(dev), seed=1, stream_id=1)
+    tb = srv.submit(torch.from_numpy(bad).to(dev), seed=2, stream_id=2)
+    rg, rb = srv.wait(tg, 30000.0), srv.wait(tb, 30000.0)
+    assert rb["status"] == mgp.MGP_EWEIGHTS and (srv.outputs(rb)[0] == -1).all()
+    assert rg["status"] == 0
+    np.testing.assert_array_equal(srv.outputs(rg)[0], oracle.resample(good, "megopolis", rg["B"], 1, stream_id=1))
+    srv.release(tg)
+    srv.release(tb)
+    srv.close()
