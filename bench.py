@@ -319,7 +319,8 @@ def main():
         "phase_ms": {k: float(np.mean(v)) for k, v in per.items()},
         "hbm_frac_effective": (step_bytes / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
         "roofline": {
-            "kernel": f"k_resample<{args.variant}> (accept loop)",
+            "kernel": "k_megopolis_mirror<4> (accept loop)" if args.variant == "megopolis" else
+                      f"k_resample<{args.variant}> (accept loop)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -122,8 +122,10 @@ def test_invalid_request_is_isolated(env):
     good = inputs.gaussian_weights(3000, 2.0, 1)
     bad = good.copy()
     bad[10] = np.nan
-    tg = srv.submit(torch.from_numpy(good).to(dev), seed=1, stream_id=1)
-    tb = srv.submit(torch.from_numpy(bad).to(dev), seed=2, stream_id=2)
+    # the weights must stay alive until the requests complete
+    wg, wb = torch.from_numpy(good).to(dev), torch.from_numpy(bad).to(dev)
+    tg = srv.submit(wg, seed=1, stream_id=1)
+    tb = srv.submit(wb, seed=2, stream_id=2)
     rg, rb = srv.wait(tg, 30000.0), srv.wait(tb, 30000.0)
     assert rb["status"] == mgp.MGP_EWEIGHTS and (srv.outputs(rb)[0] == -1).all()
     assert rg["status"] == 0
