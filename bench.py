@@ -187,7 +187,7 @@ def batched_section(torch, mgp, inputs, runs):
     }
 
 
-def serving_section(torch, mgp, inputs, n_requests):
+def serving_section(torch, mgp, inputs, n_requests, streams=4, max_batch=8, max_particles=1 << 22):
     """Poisson stream of requests, N = round(2^U(12, 22)), y ~ U[0, 4], D = 16
     states resident on the device, Megopolis, admitted by HBM budget. The
     arrival rate is 70% of the capacity measured with all requests queued at
@@ -207,7 +207,8 @@ def serving_section(torch, mgp, inputs, n_requests):
     torch.cuda.synchronize()
 
     def run(budget, rate, count, open_loop=True):
-        srv = mgp.Server("megopolis", d=16, hbm_budget=budget, streams=4, max_batch=32)
+        srv = mgp.Server("megopolis", d=16, hbm_budget=budget, streams=streams, max_batch=max_batch,
+                         max_batch_particles=max_particles)
         arrivals = np.cumsum(np.random.Generator(np.random.PCG64(7)).exponential(1.0 / rate, count)) if open_loop \
             else np.zeros(count)
         tickets = [None] * count
@@ -249,7 +250,7 @@ def serving_section(torch, mgp, inputs, n_requests):
     main_run = run(16 << 30, rate, n_requests)
     tight = run(2 << 30, rate, max(500, n_requests // 4))
     return {"workload": "Poisson requests, N=round(2^U(12,22)), y~U[0,4], D=16 states resident, Megopolis, "
-                        "4 streams, micro-batches <= 32",
+                        f"{streams} streams, micro-batches <= {max_batch} requests / {max_particles} particles",
             "capacity_particles_per_s": cap["particles_per_s"], "capacity_requests_per_s": capacity_rps,
             "arrival_rate_per_s": rate, "budget_16GB": main_run, "budget_2GB": tight}
 

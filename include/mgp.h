@@ -167,6 +167,7 @@ typedef struct mgp_batch_info {
     int64_t tiles;               /* accept-loop tiles */
     int64_t device_bytes;        /* device memory owned by the plan */
     double est_particle_steps;   /* sum of n * B from the plan-time reduction */
+    int64_t grid;                /* workgroups of the accept-loop launch */
 } mgp_batch_info;
 
 typedef struct mgp_batch_plan mgp_batch_plan;

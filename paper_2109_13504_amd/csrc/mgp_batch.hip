@@ -158,8 +158,11 @@ __global__ __launch_bounds__(BT) void k_batch_loop_grid(const FilterDev* __restr
 }
 
 // Persistent blocks: block b serves the queue of XCD b mod nq first, then
-// steals from the others; it exits once every queue is exhausted (each pull
-// advances a counter, so every block reaches the exit).
+// steals from the others; it exits once every queue is exhausted (each grab
+// advances a counter, so every block reaches the exit). A grab claims a
+// chunk of tiles sized to what is left (guided self-scheduling: about
+// remaining / (2 * blocks per queue), at least 1), because device-scope
+// atomics on one counter serialize across the chip.
 template <int V, int BT, int P>
 __global__ __launch_bounds__(BT) void k_batch_loop_persistent(const FilterDev* __restrict__ fd,
                                                               const mgp_stats* __restrict__ stats,
@@ -167,30 +170,42 @@ __global__ __launch_bounds__(BT) void k_batch_loop_persistent(const FilterDev* _
                                                               const uint32_t* __restrict__ qoff,
                                                               uint32_t* __restrict__ qcount, uint32_t nq, uint32_t d)
 {
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_first, s_last;
     const uint32_t home = blockIdx.x % nq;
+    const uint32_t per_queue = (gridDim.x + nq - 1) / nq;
     uint32_t tried = 0;
+    uint32_t seen = 0;  // last counter value this block saw on the current queue
     for (;;) {
         if (threadIdx.x == 0) {
-            uint32_t t = kNoFilter;
+            uint32_t first = kNoFilter, last = 0;
             while (tried < nq) {
                 const uint32_t q = (home + tried) % nq;
                 const uint32_t len = qoff[q + 1] - qoff[q];
-                const uint32_t idx = atomicAdd(&qcount[q], 1u);
+                const uint32_t left = len > seen ? len - seen : 0;
+                uint32_t chunk = left / (2u * per_queue);
+                chunk = chunk < 1u ? 1u : (chunk > 64u ? 64u : chunk);
+                const uint32_t idx = atomicAdd(&qcount[q], chunk);
                 if (idx < len) {
-                    t = qoff[q] + idx;
+                    first = qoff[q] + idx;
+                    last = qoff[q] + (idx + chunk < len ? idx + chunk : len);
+                    seen = idx + chunk;
                     break;
                 }
                 ++tried;
+                seen = 0;
             }
-            s_tile = t;
+            s_first = first;
+            s_last = last;
         }
         __syncthreads();
-        const uint32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+        const uint32_t first = __builtin_amdgcn_readfirstlane(s_first);
+        const uint32_t last = __builtin_amdgcn_readfirstlane(s_last);
         __syncthreads();
-        if (t == kNoFilter) break;
-        const LTile tile = tiles[t];
-        process_tile<V, BT, P>(fd[tile.f], &stats[tile.f], tile.start, d);
+        if (first == kNoFilter) break;
+        for (uint32_t t = first; t < last; ++t) {
+            const LTile tile = tiles[t];
+            process_tile<V, BT, P>(fd[tile.f], &stats[tile.f], tile.start, d);
+        }
     }
 }
 
@@ -317,25 +332,43 @@ void build_tile_table(const std::vector<uint32_t>& n, const std::vector<double>&
 {
     const uint32_t tile = (uint32_t)(sh.bt * sh.ppt);
     const int count = (int)n.size();
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    // Work items are chunks of whole tiles: a filter is cut into chunks of
+    // about total / (16 nx) particles, so that a few large filters still
+    // spread over every XCD while small filters stay whole (one L2 each).
+    uint64_t total = 0;
+    for (uint32_t x : n) total += x;
+    uint64_t chunk = (total + 16ull * nx - 1) / (16ull * nx);
+    chunk = std::max<uint64_t>(tile, (chunk + tile - 1) / tile * tile);
+    struct Item {
+        uint32_t f, start, stop;
+        double cost;
+    };
+    std::vector<Item> items;
+    for (int f = 0; f < count; ++f) {
+        const double per = cost[f] / std::max<uint32_t>(1u, n[f]);
+        for (uint64_t st = 0; st < n[f]; st += chunk) {
+            const uint32_t stop = (uint32_t)std::min<uint64_t>(n[f], st + chunk);
+            items.push_back(Item{(uint32_t)f, (uint32_t)st, stop, per * (stop - st)});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
     std::vector<double> load(nx, 0.0);
-    std::vector<std::vector<int>> per(nx);
-    for (int f : order) {
+    std::vector<std::vector<Item>> per(nx);
+    for (const Item& it : items) {
         int best = 0;
         for (int x = 1; x < nx; ++x)
             if (load[x] < load[best]) best = x;
-        load[best] += cost[f];
-        per[best].push_back(f);
+        load[best] += it.cost;
+        per[best].push_back(it);
     }
     std::vector<std::vector<LTile>> lists(nx);
     for (int x = 0; x < nx; ++x) {
         // costlier tiles (larger cost per particle) first inside the XCD
-        std::stable_sort(per[x].begin(), per[x].end(),
-                         [&](int a, int b) { return cost[a] / n[a] > cost[b] / n[b]; });
-        for (int f : per[x])
-            for (uint32_t st = 0; st < n[f]; st += tile) lists[x].push_back(LTile{(uint32_t)f, st});
+        std::stable_sort(per[x].begin(), per[x].end(), [&](const Item& a, const Item& b) {
+            return cost[a.f] / n[a.f] > cost[b.f] / n[b.f];
+        });
+        for (const Item& it : per[x])
+            for (uint32_t st = it.start; st < it.stop; st += tile) lists[x].push_back(LTile{it.f, st});
     }
     table.clear();
     for (int x = 0; x <= kMaxXcd; ++x) qoff[x] = 0;
@@ -856,6 +889,7 @@ int mgp_batch_plan_info(const mgp_batch_plan* p, mgp_batch_info* info)
     info->tiles = p->n_table;
     info->device_bytes = (int64_t)p->dmem_bytes + (int64_t)p->n_ltiles * (int64_t)sizeof(LTile);
     info->est_particle_steps = p->est_steps;
+    info->grid = p->grid;
     return MGP_OK;
 }
 

@@ -119,7 +119,9 @@ struct Slot {
     LTile* d_lt = nullptr;
     Partial* d_parts = nullptr;
     mgp_stats* d_stats = nullptr;
-    uint32_t* d_q = nullptr;  // queue counters [kMaxXcd + 1] then offsets [kMaxXcd + 1]
+    uint32_t* d_q = nullptr;     // queue counters [kMaxXcd + 1]
+    uint32_t* d_qoff = nullptr;  // queue offsets [kMaxXcd + 1]
+    size_t lt_offset = 0;        // start of the loop tiles in the upload region
     char* hmem = nullptr;
     FilterDev* h_fd = nullptr;
     RTile* h_rt = nullptr;
@@ -258,15 +260,13 @@ int launch_batch(mgp_server* s, Slot& sl, const std::vector<Req*>& rs)
     if (table.size() > s->cap_lt) return fail(MGP_ERANGE, "micro-batch exceeds the slot tables");
     memcpy(sl.h_lt, table.data(), table.size() * sizeof(LTile));
     hipStream_t st = sl.stream;
-    if (hipMemcpyAsync(sl.d_fd, sl.h_fd, count * sizeof(FilterDev), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(sl.d_rt, sl.h_rt, nrt * sizeof(RTile), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(sl.d_lt, sl.h_lt, table.size() * sizeof(LTile), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(sl.d_q + (kMaxXcd + 1), sl.h_qoff, (kMaxXcd + 1) * sizeof(uint32_t), hipMemcpyHostToDevice,
-                       st) != hipSuccess)
+    // one upload: the qoff, filter and tile tables share one layout on both sides
+    const size_t upload = sl.lt_offset + table.size() * sizeof(LTile);
+    if (hipMemcpyAsync(sl.dmem, sl.hmem, upload, hipMemcpyHostToDevice, st) != hipSuccess)
         return fail(MGP_EHIP, "uploading micro-batch tables failed");
     const uint32_t grid = (uint32_t)table.size();
     int rc = enqueue_batch(s->variant, s->shape, sl.d_fd, count, sl.d_rt, nrt, sl.d_parts, sl.d_stats, sl.d_lt, grid,
-                           sl.d_q + (kMaxXcd + 1), sl.d_q, (uint32_t)s->nxcd, (uint32_t)s->cfg.d, st);
+                           sl.d_qoff, sl.d_q, (uint32_t)s->nxcd, (uint32_t)s->cfg.d, st);
     if (rc) return rc;
     if (hipMemcpyAsync(sl.h_stats, sl.d_stats, count * sizeof(mgp_stats), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipEventRecord(sl.done, st) != hipSuccess)
@@ -413,45 +413,61 @@ void scheduler(mgp_server* s)
     }
 }
 
-int alloc_slot(mgp_server* s, Slot& sl)
+// A slot's tables: the uploaded part [qoff | filters | reduce tiles | loop
+// tiles] has the same layout on the host (pinned) and the device, so one
+// copy of its used prefix uploads a micro-batch.
+struct SlotLayout {
+    size_t qoff, fd, rt, lt, upload_end;  // upload region
+    size_t parts, stats, qcount, dev_end; // device-only region
+    size_t h_stats, host_end;             // host-only region
+};
+
+SlotLayout slot_layout(const mgp_server* s)
 {
+    SlotLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = (off + bytes + 255) & ~(size_t)255;
         return o;
     };
-    const size_t o_fd = take(sizeof(FilterDev) * s->cap_f);
-    const size_t o_rt = take(sizeof(RTile) * s->cap_rt);
-    const size_t o_lt = take(sizeof(LTile) * s->cap_lt);
-    const size_t o_parts = take(sizeof(Partial) * s->cap_rt);
-    const size_t o_stats = take(sizeof(mgp_stats) * s->cap_f);
-    const size_t o_q = take(sizeof(uint32_t) * 2 * (kMaxXcd + 1));
-    const size_t dbytes = off;
-    off = 0;
-    const size_t h_fd = take(sizeof(FilterDev) * s->cap_f);
-    const size_t h_rt = take(sizeof(RTile) * s->cap_rt);
-    const size_t h_lt = take(sizeof(LTile) * s->cap_lt);
-    const size_t h_stats = take(sizeof(mgp_stats) * s->cap_f);
-    const size_t h_q = take(sizeof(uint32_t) * (kMaxXcd + 1));
-    const size_t hbytes = off;
+    L.qoff = take(sizeof(uint32_t) * (kMaxXcd + 1));
+    L.fd = take(sizeof(FilterDev) * s->cap_f);
+    L.rt = take(sizeof(RTile) * s->cap_rt);
+    L.lt = take(sizeof(LTile) * s->cap_lt);
+    L.upload_end = off;
+    L.parts = take(sizeof(Partial) * s->cap_rt);
+    L.stats = take(sizeof(mgp_stats) * s->cap_f);
+    L.qcount = take(sizeof(uint32_t) * (kMaxXcd + 1));
+    L.dev_end = off;
+    off = L.upload_end;
+    L.h_stats = take(sizeof(mgp_stats) * s->cap_f);
+    L.host_end = off;
+    return L;
+}
+
+int alloc_slot(mgp_server* s, Slot& sl)
+{
+    const SlotLayout L = slot_layout(s);
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
         return fail(MGP_EHIP, "creating a server stream failed");
-    if (hipMalloc(&sl.dmem, dbytes) != hipSuccess) return fail(MGP_ENOMEM, "server tables: hipMalloc failed");
-    if (hipHostMalloc(reinterpret_cast<void**>(&sl.hmem), hbytes) != hipSuccess)
+    if (hipMalloc(&sl.dmem, L.dev_end) != hipSuccess) return fail(MGP_ENOMEM, "server tables: hipMalloc failed");
+    if (hipHostMalloc(reinterpret_cast<void**>(&sl.hmem), L.host_end) != hipSuccess)
         return fail(MGP_ENOMEM, "server staging: hipHostMalloc failed");
-    sl.d_fd = reinterpret_cast<FilterDev*>(sl.dmem + o_fd);
-    sl.d_rt = reinterpret_cast<RTile*>(sl.dmem + o_rt);
-    sl.d_lt = reinterpret_cast<LTile*>(sl.dmem + o_lt);
-    sl.d_parts = reinterpret_cast<Partial*>(sl.dmem + o_parts);
-    sl.d_stats = reinterpret_cast<mgp_stats*>(sl.dmem + o_stats);
-    sl.d_q = reinterpret_cast<uint32_t*>(sl.dmem + o_q);
-    sl.h_fd = reinterpret_cast<FilterDev*>(sl.hmem + h_fd);
-    sl.h_rt = reinterpret_cast<RTile*>(sl.hmem + h_rt);
-    sl.h_lt = reinterpret_cast<LTile*>(sl.hmem + h_lt);
-    sl.h_stats = reinterpret_cast<mgp_stats*>(sl.hmem + h_stats);
-    sl.h_qoff = reinterpret_cast<uint32_t*>(sl.hmem + h_q);
+    sl.d_fd = reinterpret_cast<FilterDev*>(sl.dmem + L.fd);
+    sl.d_rt = reinterpret_cast<RTile*>(sl.dmem + L.rt);
+    sl.d_lt = reinterpret_cast<LTile*>(sl.dmem + L.lt);
+    sl.d_parts = reinterpret_cast<Partial*>(sl.dmem + L.parts);
+    sl.d_stats = reinterpret_cast<mgp_stats*>(sl.dmem + L.stats);
+    sl.d_q = reinterpret_cast<uint32_t*>(sl.dmem + L.qcount);
+    sl.d_qoff = reinterpret_cast<uint32_t*>(sl.dmem + L.qoff);
+    sl.h_fd = reinterpret_cast<FilterDev*>(sl.hmem + L.fd);
+    sl.h_rt = reinterpret_cast<RTile*>(sl.hmem + L.rt);
+    sl.h_lt = reinterpret_cast<LTile*>(sl.hmem + L.lt);
+    sl.h_stats = reinterpret_cast<mgp_stats*>(sl.hmem + L.h_stats);
+    sl.h_qoff = reinterpret_cast<uint32_t*>(sl.hmem + L.qoff);
+    sl.lt_offset = L.lt;
     return MGP_OK;
 }
 

@@ -57,7 +57,8 @@ class mgp_batch_info(ctypes.Structure):
     _fields_ = [("filters", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("particles_per_thread", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("from_cache", ctypes.c_int32), ("xcds", ctypes.c_int32), ("particles", ctypes.c_int64),
-                ("tiles", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("est_particle_steps", ctypes.c_double)]
+                ("tiles", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("est_particle_steps", ctypes.c_double),
+                ("grid", ctypes.c_int64)]
 
 
 class mgp_server_config(ctypes.Structure):

@@ -25,7 +25,23 @@ int main(void)
     S(mgp_batch_info); F(mgp_batch_info, filters); F(mgp_batch_info, block_threads);
     F(mgp_batch_info, particles_per_thread); F(mgp_batch_info, schedule); F(mgp_batch_info, from_cache);
     F(mgp_batch_info, xcds); F(mgp_batch_info, particles); F(mgp_batch_info, tiles); F(mgp_batch_info, device_bytes);
-    F(mgp_batch_info, est_particle_steps);
+    F(mgp_batch_info, est_particle_steps); F(mgp_batch_info, grid);
+    S(mgp_server_config); F(mgp_server_config, variant); F(mgp_server_config, d);
+    F(mgp_server_config, partition_bytes); F(mgp_server_config, b_max); F(mgp_server_config, hbm_budget);
+    F(mgp_server_config, streams); F(mgp_server_config, max_batch); F(mgp_server_config, max_batch_particles);
+    F(mgp_server_config, max_n); F(mgp_server_config, simulate); F(mgp_server_config, sim_us_fixed);
+    F(mgp_server_config, sim_ns_per_particle); F(mgp_server_config, sim_fail_every); F(mgp_server_config, reserved);
+    S(mgp_request); F(mgp_request, w_dev); F(mgp_request, n); F(mgp_request, B); F(mgp_request, epsilon);
+    F(mgp_request, seed); F(mgp_request, stream_id); F(mgp_request, reserved); F(mgp_request, states_dev);
+    S(mgp_request_result); F(mgp_request_result, state); F(mgp_request_result, status); F(mgp_request_result, B);
+    F(mgp_request_result, n); F(mgp_request_result, ancestors_dev); F(mgp_request_result, out_states_dev);
+    F(mgp_request_result, t_submit); F(mgp_request_result, t_admit); F(mgp_request_result, t_dispatch);
+    F(mgp_request_result, t_done);
+    S(mgp_server_stats); F(mgp_server_stats, submitted); F(mgp_server_stats, admitted);
+    F(mgp_server_stats, completed); F(mgp_server_stats, failed); F(mgp_server_stats, cancelled);
+    F(mgp_server_stats, released); F(mgp_server_stats, micro_batches); F(mgp_server_stats, queued);
+    F(mgp_server_stats, in_flight); F(mgp_server_stats, pool_bytes); F(mgp_server_stats, pool_in_use);
+    F(mgp_server_stats, pool_peak); F(mgp_server_stats, max_concurrent_batches);
     printf("\"end\": 0\n}\n");
     return 0;
 }
