@@ -89,16 +89,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_batch_finalize(const FilterD
 __device__ __forceinline__ void gather_row(const FilterDev& F, uint32_t i, int32_t k, uint32_t d)
 {
     if (!F.states || d == 0) return;
+    // outputs are streamed past the L2 (written once, never read here)
     if (F.rows4) {
         const float4* src = reinterpret_cast<const float4*>(F.states);
         float4* dst = reinterpret_cast<float4*>(F.out);
         const uint32_t d4 = d / 4u;
-        for (uint32_t c = 0; c < d4; ++c)
-            dst[(uint64_t)i * d4 + c] =
-                k >= 0 ? src[(uint64_t)k * d4 + c] : make_float4(NAN, NAN, NAN, NAN);
+        for (uint32_t c = 0; c < d4; ++c) {
+            const float4 v = k >= 0 ? src[(uint64_t)k * d4 + c] : make_float4(NAN, NAN, NAN, NAN);
+            float4* o = &dst[(uint64_t)i * d4 + c];
+            __builtin_nontemporal_store(v.x, &o->x);
+            __builtin_nontemporal_store(v.y, &o->y);
+            __builtin_nontemporal_store(v.z, &o->z);
+            __builtin_nontemporal_store(v.w, &o->w);
+        }
     } else {
         for (uint32_t c = 0; c < d; ++c)
-            F.out[(uint64_t)i * d + c] = k >= 0 ? F.states[(uint64_t)k * d + c] : NAN;
+            __builtin_nontemporal_store(k >= 0 ? F.states[(uint64_t)k * d + c] : NAN, &F.out[(uint64_t)i * d + c]);
     }
 }
 
@@ -243,6 +249,8 @@ static bool launch_loop_variant(const LoopShape& sh, const LoopArgs& a, hipStrea
         if (sh.bt == 128 && sh.ppt == 4) return launch_loop_shape<V, 128, 4>(sh.sched, a, s), true;
         if (sh.bt == 128 && sh.ppt == 2) return launch_loop_shape<V, 128, 2>(sh.sched, a, s), true;
         if (sh.bt == 64 && sh.ppt == 4) return launch_loop_shape<V, 64, 4>(sh.sched, a, s), true;
+        if (sh.bt == 64 && sh.ppt == 8) return launch_loop_shape<V, 64, 8>(sh.sched, a, s), true;
+        if (sh.bt == 128 && sh.ppt == 8) return launch_loop_shape<V, 128, 8>(sh.sched, a, s), true;
         return false;
     } else {
         if (sh.ppt != 1) return false;
@@ -282,6 +290,8 @@ static int occupancy_variant(const LoopShape& sh)
         if (sh.bt == 256 && sh.ppt == 1) return occupancy_of<V, 256, 1>();
         if (sh.bt == 128 && sh.ppt == 4) return occupancy_of<V, 128, 4>();
         if (sh.bt == 128 && sh.ppt == 2) return occupancy_of<V, 128, 2>();
+        if (sh.bt == 64 && sh.ppt == 8) return occupancy_of<V, 64, 8>();
+        if (sh.bt == 128 && sh.ppt == 8) return occupancy_of<V, 128, 8>();
         return occupancy_of<V, 64, 4>();
     } else {
         if (sh.bt == 256) return occupancy_of<V, 256, 1>();
@@ -311,6 +321,8 @@ static std::vector<LoopShape> candidate_shapes(int variant)
             c.push_back({128, 4, sched});
             c.push_back({128, 2, sched});
             c.push_back({64, 4, sched});
+            c.push_back({64, 8, sched});
+            c.push_back({128, 8, sched});
         } else {
             c.push_back({256, 1, sched});
             c.push_back({128, 1, sched});

@@ -15,6 +15,7 @@ constexpr int kVersion = 100;               // 0.1.0
 constexpr uint32_t kReduceThreads = 256;    // reduce / finalize block
 constexpr uint32_t kLoopThreads = 256;      // accept-loop block (4 waves of 64)
 constexpr uint32_t kMaxPartials = 4096;     // reduce blocks per filter, at most
+constexpr uint32_t kReduceChunk = 2048;     // weights per reduce block (before the kMaxPartials cap)
 constexpr uint32_t kDefaultBMax = 65536;
 constexpr uint32_t kBMaxLimit = 1u << 24;
 

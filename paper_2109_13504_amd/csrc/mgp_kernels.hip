@@ -150,7 +150,12 @@ __global__ __launch_bounds__(256) void k_gather_vec4(const float4* __restrict__ 
         } else {
             v = make_float4(NAN, NAN, NAN, NAN);
         }
-        out[t] = v;
+        // the output is written once and not read here: stream it past the
+        // L2 so that the ancestor rows being read stay cached
+        __builtin_nontemporal_store(v.x, &out[t].x);
+        __builtin_nontemporal_store(v.y, &out[t].y);
+        __builtin_nontemporal_store(v.z, &out[t].z);
+        __builtin_nontemporal_store(v.w, &out[t].w);
     }
 }
 
@@ -163,7 +168,7 @@ __global__ __launch_bounds__(256) void k_gather_scalar(const float* __restrict__
         const uint64_t row = t / d;
         const uint32_t c = (uint32_t)(t - row * d);
         const int32_t k = anc[row];
-        out[t] = (k >= 0 && (uint32_t)k < n_states) ? states[(uint64_t)k * d + c] : NAN;
+        __builtin_nontemporal_store((k >= 0 && (uint32_t)k < n_states) ? states[(uint64_t)k * d + c] : NAN, &out[t]);
     }
 }
 
@@ -172,8 +177,8 @@ __global__ __launch_bounds__(256) void k_gather_scalar(const float* __restrict__
 // ---------------------------------------------------------------------------
 uint32_t reduce_blocks(uint32_t n)
 {
-    // about 2048 weights per block, at most kMaxPartials blocks
-    uint64_t g = ((uint64_t)n + 2047u) / 2048u;
+    // about kReduceChunk weights per block, at most kMaxPartials blocks
+    uint64_t g = ((uint64_t)n + kReduceChunk - 1u) / kReduceChunk;
     if (g > kMaxPartials) g = kMaxPartials;
     if (g < 1) g = 1;
     return (uint32_t)g;

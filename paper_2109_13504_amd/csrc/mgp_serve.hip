@@ -543,7 +543,7 @@ int mgp_server_create(const mgp_server_config* cfg, mgp_server** out)
     s->shape = s->variant == kMegopolis ? LoopShape{64, 4, 1} : LoopShape{256, 1, 1};
     const uint32_t tile = (uint32_t)(s->shape.bt * s->shape.ppt);
     s->cap_f = (uint32_t)cfg->max_batch;
-    s->cap_rt = (uint32_t)(s->max_particles / 2048 + 2 * (int64_t)cfg->max_batch + 1);
+    s->cap_rt = (uint32_t)(s->max_particles / kReduceChunk + 2 * (int64_t)cfg->max_batch + 1);
     s->t0 = std::chrono::steady_clock::now();
     s->slots.resize(cfg->streams);
     if (cfg->simulate) {
