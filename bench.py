@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-filters section")
     ap.add_argument("--batch-runs", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant sweep at N=2^22")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
@@ -185,6 +186,36 @@ def batched_section(torch, mgp, inputs, runs):
                         "from_cache": bool(info["from_cache"])},
         "plan_create_s": plan_s,
     }
+
+
+def sweep_section(torch, mgp, inputs):
+    """The paper's timing experiment on this GPU: resample time (reduction, B,
+    accept loop; no gather) at N = 2^22 for Megopolis, Metropolis, C1 and C2
+    at 128 and 2048 bytes, y = 0..4, eps = 0.01; median of 5 runs."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    n = 1 << 22
+    r = mgp.Resampler(n)
+    anc = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    rows = [("megopolis", 128), ("metropolis", 128), ("c1", 128), ("c1", 2048), ("c2", 128), ("c2", 2048)]
+    out = {}
+    for y in range(5):
+        w = torch.from_numpy(inputs.gaussian_weights(n, float(y), 0)).to(dev)
+        for v, ps in rows:
+            key = f"{v}-ps{ps}" if v in ("c1", "c2") else v
+            times = []
+            for k in range(6):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                r.resample(w, v, epsilon=0.01, seed=k, partition_bytes=ps, out=anc)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if k:
+                    times.append(a.elapsed_time(b))
+            out.setdefault(key, {})[f"y{y}"] = {"ms": float(np.median(times)), "B": r.last_stats()["B"]}
+    return {"workload": "N=2^22, Gaussian-likelihood weights, eps=0.01; resample = reduction + B + accept loop "
+                        "(no gather); median of 5 runs", "ms": out}
 
 
 def serving_section(torch, mgp, inputs, n_requests, streams=4, max_batch=8, max_particles=1 << 22):
@@ -363,6 +394,10 @@ def main():
         bt = result["batched"]
         log(f"[bench] batched: graph {bt['graph_ms']:.3f} ms/run, separate {bt['separate_ms']:.3f} ms/run "
             f"-> {bt['speedup_vs_separate']:.2f}x, shape {bt['tuned_shape']}")
+
+    if not args.no_sweep:
+        log("[bench] per-variant sweep at N=2^22")
+        result["paper_sweep"] = sweep_section(torch, mgp, inputs)
 
     if not args.no_serving:
         log("[bench] serving")
