@@ -276,6 +276,14 @@ int mgp_server_poll(mgp_server* server, uint64_t ticket, mgp_request_result* res
  * (MGP_EBUSY then; a negative timeout waits forever). */
 int mgp_server_wait(mgp_server* server, uint64_t ticket, double timeout_ms, mgp_request_result* result);
 
+/* Copies a finished request's outputs into caller buffers on `stream`:
+ * ancestors_dev (n int32) and, if the request had states and out_states_dev
+ * is not NULL, out_states_dev (n x d fp32). MGP_EBUSY if not finished. The
+ * copy reads server memory: release the ticket only after `stream` has
+ * finished it. */
+int mgp_server_copy_outputs(mgp_server* server, uint64_t ticket, int32_t* ancestors_dev, float* out_states_dev,
+                            void* stream);
+
 /* Cancels a request that is still queued; MGP_EBUSY once it was admitted. */
 int mgp_server_cancel(mgp_server* server, uint64_t ticket);
 

@@ -635,6 +635,37 @@ int mgp_server_wait(mgp_server* s, uint64_t ticket, double timeout_ms, mgp_reque
     return MGP_OK;
 }
 
+int mgp_server_copy_outputs(mgp_server* s, uint64_t ticket, int32_t* anc, float* out, void* stream)
+{
+    clear_error();
+    if (!s || !anc) return fail(MGP_EINVAL, "NULL argument");
+    if (s->cfg.simulate) return fail(MGP_EINVAL, "a simulated server has no outputs");
+    const char* src_anc = nullptr;
+    const char* src_out = nullptr;
+    size_t anc_bytes = 0, out_bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return fail(MGP_EINVAL, "unknown ticket");
+        const Req& q = it->second;
+        if (q.state != MGP_REQ_DONE || !q.has_out) return fail(MGP_EBUSY, "request has no outputs (not done)");
+        src_anc = s->pool_base + q.out_off;
+        anc_bytes = 4ull * (uint64_t)q.in.n;
+        if (q.out_bytes > q.anc_bytes) {
+            src_out = src_anc + q.anc_bytes;
+            out_bytes = 4ull * (uint64_t)q.in.n * (uint64_t)s->cfg.d;
+        }
+    }
+    // the outputs stay allocated until release, which the caller orders
+    // after this copy
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(anc, src_anc, anc_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(MGP_EHIP, "copying ancestors failed");
+    if (out && src_out && hipMemcpyAsync(out, src_out, out_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(MGP_EHIP, "copying gathered states failed");
+    return MGP_OK;
+}
+
 int mgp_server_cancel(mgp_server* s, uint64_t ticket)
 {
     clear_error();

@@ -131,11 +131,12 @@ def lib():
         L.mgp_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(mgp_request_result)]
         L.mgp_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(mgp_request_result)]
         L.mgp_server_cancel.argtypes = [_vp, ctypes.c_uint64]
+        L.mgp_server_copy_outputs.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, _vp]
         L.mgp_server_release.argtypes = [_vp, ctypes.c_uint64]
         L.mgp_server_get_stats.argtypes = [_vp, ctypes.POINTER(mgp_server_stats)]
         L.mgp_server_destroy.argtypes = [_vp]
         for f in ("mgp_server_create", "mgp_server_submit", "mgp_server_poll", "mgp_server_wait", "mgp_server_cancel",
-                  "mgp_server_release", "mgp_server_get_stats", "mgp_server_destroy"):
+                  "mgp_server_copy_outputs", "mgp_server_release", "mgp_server_get_stats", "mgp_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
@@ -262,6 +263,11 @@ def mgp_server_wait(server: int, ticket: int, timeout_ms: float = -1.0) -> dict:
 
 def mgp_server_cancel(server: int, ticket: int) -> None:
     _check(lib().mgp_server_cancel(server, ticket), "mgp_server_cancel")
+
+
+def mgp_server_copy_outputs(server: int, ticket: int, ancestors_dev: int, out_states_dev: int, stream: int) -> None:
+    _check(lib().mgp_server_copy_outputs(server, ticket, ancestors_dev, out_states_dev or None, stream or None),
+           "mgp_server_copy_outputs")
 
 
 def mgp_server_release(server: int, ticket: int) -> None:
@@ -454,16 +460,15 @@ class Server:
     def stats(self) -> dict:
         return mgp_server_get_stats(self.handle)
 
-    def outputs(self, result: dict):
-        """Copies a finished request's ancestors (and gathered states) to host numpy arrays."""
+    def outputs(self, ticket: int, result: dict):
+        """Copies a finished request's ancestors (and gathered states) into new
+        device tensors with mgp_server_copy_outputs; returns host numpy arrays."""
         torch = _torch()
         n = result["n"]
         anc = torch.empty(n, dtype=torch.int32, device="cuda")
-        _hip_copy(anc.data_ptr(), result["ancestors_dev"], 4 * n)
-        out = None
-        if result["out_states_dev"]:
-            out = torch.empty((n, self.d), dtype=torch.float32, device="cuda")
-            _hip_copy(out.data_ptr(), result["out_states_dev"], 4 * n * self.d)
+        out = torch.empty((n, self.d), dtype=torch.float32, device="cuda") if result["out_states_dev"] else None
+        mgp_server_copy_outputs(self.handle, ticket, anc.data_ptr(), out.data_ptr() if out is not None else 0,
+                                current_stream())
         torch.cuda.synchronize()
         return anc.cpu().numpy(), (out.cpu().numpy() if out is not None else None)
 
@@ -477,23 +482,3 @@ class Server:
             self.close()
         except Exception:
             pass
-
-
-def _hip_copy(dst: int, src: int, nbytes: int) -> None:
-    """Device-to-device copy between raw device addresses on torch's current stream."""
-    rc = _copy_lib().hipMemcpyDtoDAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes),
-                                        ctypes.c_void_p(current_stream()))
-    if rc != 0:
-        raise RuntimeError(f"hipMemcpyDtoDAsync failed ({rc})")
-
-
-_hip = None
-
-
-def _copy_lib():
-    global _hip
-    if _hip is None:
-        _hip = ctypes.CDLL("libamdhip64.so")
-        _hip.hipMemcpyDtoDAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
-        _hip.hipMemcpyDtoDAsync.restype = ctypes.c_int
-    return _hip

@@ -43,7 +43,7 @@ def run_alone(srv, reqs):
         t = srv.submit(r["w"], seed=r["seed"], stream_id=r["stream_id"], states=r["states"])
         res = srv.wait(t, 60000.0)
         assert res["state"] == 2, res
-        out.append((res["B"], *srv.outputs(res)))
+        out.append((res["B"], *srv.outputs(t, res)))
         srv.release(t)
     return out
 
@@ -68,7 +68,7 @@ def run_mixed(srv, reqs):
     for t in tickets:
         res = srv.wait(t, 60000.0)
         assert res["state"] == 2, res
-        out.append((res["B"], *srv.outputs(res)))
+        out.append((res["B"], *srv.outputs(t, res)))
         srv.release(t)
     return out
 
@@ -127,9 +127,9 @@ def test_invalid_request_is_isolated(env):
     tg = srv.submit(wg, seed=1, stream_id=1)
     tb = srv.submit(wb, seed=2, stream_id=2)
     rg, rb = srv.wait(tg, 30000.0), srv.wait(tb, 30000.0)
-    assert rb["status"] == mgp.MGP_EWEIGHTS and (srv.outputs(rb)[0] == -1).all()
+    assert rb["status"] == mgp.MGP_EWEIGHTS and (srv.outputs(tb, rb)[0] == -1).all()
     assert rg["status"] == 0
-    np.testing.assert_array_equal(srv.outputs(rg)[0], oracle.resample(good, "megopolis", rg["B"], 1, stream_id=1))
+    np.testing.assert_array_equal(srv.outputs(tg, rg)[0], oracle.resample(good, "megopolis", rg["B"], 1, stream_id=1))
     srv.release(tg)
     srv.release(tb)
     srv.close()
