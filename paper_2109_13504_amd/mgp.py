@@ -303,6 +303,12 @@ def decode_stats(stats_tensor) -> dict:
     return {k: rec[k].item() for k in STATS_DTYPE.names}
 
 
+def _require_weights(w) -> None:
+    torch = _torch()
+    if w.dtype != torch.float32 or not w.is_cuda or not w.is_contiguous() or w.dim() != 1:
+        raise ValueError("weights must be a contiguous 1-D fp32 device tensor")
+
+
 class Resampler:
     """Holds a device workspace sized for (n_max, b_max) and calls mgp_resample."""
 
@@ -316,8 +322,8 @@ class Resampler:
 
     def resample(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
                  stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+        _require_weights(w)
         torch = _torch()
-        assert w.dtype == torch.float32 and w.is_cuda and w.is_contiguous() and w.dim() == 1
         n = w.numel()
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=w.device)
@@ -329,6 +335,7 @@ class Resampler:
     def compute_B(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
                   stream_id: int = 0, partition_bytes: int = 128, stream: int | None = None) -> None:
         """Reduction, B and offsets only (asynchronous; read last_stats() after a sync)."""
+        _require_weights(w)
         p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
         mgp_compute_B(w.data_ptr(), w.numel(), p, self.stats.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
                       current_stream() if stream is None else stream)
@@ -336,6 +343,7 @@ class Resampler:
     def resample_prepared(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
                           stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
         """The accept loop only, after compute_B with the same arguments."""
+        _require_weights(w)
         torch = _torch()
         n = w.numel()
         if out is None:
@@ -360,7 +368,10 @@ def resample(w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: in
 def gather(states, anc, out=None, stream: int | None = None):
     """out[i] = states[anc[i]] for fp32 states [n_states, d] on the device."""
     torch = _torch()
-    assert states.dtype == torch.float32 and states.is_cuda and states.is_contiguous()
+    if states.dtype != torch.float32 or not states.is_cuda or not states.is_contiguous() or states.dim() < 1:
+        raise ValueError("states must be a contiguous fp32 device tensor [n_states, d]")
+    if anc.dtype != torch.int32 or not anc.is_cuda or not anc.is_contiguous():
+        raise ValueError("ancestors must be a contiguous int32 device tensor")
     st2 = states.view(states.shape[0], -1)
     n_states, d = st2.shape
     n_out = anc.numel()
