@@ -81,6 +81,13 @@ def lib():
         L.mgp_oracle_choose_B.restype = ctypes.c_int
         L.mgp_oracle_gather.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32, _f32p]
         L.mgp_oracle_gather.restype = ctypes.c_int
+        L.mgp_oracle_sir_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.mgp_oracle_sir_normal.restype = ctypes.c_double
+        L.mgp_oracle_sir_predict_update.argtypes = [_f32p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double,
+                                                    ctypes.c_uint64, ctypes.c_uint32, _f32p, _f32p]
+        L.mgp_oracle_sir_predict_update.restype = None
+        L.mgp_oracle_mean.argtypes = [_f32p, ctypes.c_int32]
+        L.mgp_oracle_mean.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -212,3 +219,60 @@ def gather(states: np.ndarray, anc: np.ndarray) -> np.ndarray:
     if rc:
         raise OracleError(rc, "mgp_oracle_gather")
     return out
+
+
+# ---------------------------------------------------------------------------
+# The SIR application of Section 7 (Algorithm 6)
+# ---------------------------------------------------------------------------
+
+def sir_normal(seed: int, run: int, i: int, t: int) -> float:
+    return float(lib().mgp_oracle_sir_normal(seed, run, i, t))
+
+
+def sir_predict_update(xbar: np.ndarray, t: int, z: float, seed: int, run: int):
+    xbar = np.ascontiguousarray(xbar, dtype=np.float32)
+    x = np.empty_like(xbar)
+    w = np.empty_like(xbar)
+    lib().mgp_oracle_sir_predict_update(_ptr(xbar, _f32p), xbar.size, t, z, seed, run, _ptr(x, _f32p),
+                                        _ptr(w, _f32p))
+    return x, w
+
+
+def mean(x: np.ndarray) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    return float(lib().mgp_oracle_mean(_ptr(x, _f32p), x.size))
+
+
+def sir_step_seed(seed: int, t: int) -> int:
+    """Philox key of the resample at step t: the seed plus t * 2^32 (mod 2^64)."""
+    return (seed + (t << 32)) & 0xFFFFFFFFFFFFFFFF
+
+
+def sir_filter(x0: np.ndarray, z: np.ndarray, variant, B: int, seed: int, run: int, partition_bytes: int = 128,
+               epsilon: float = 0.1, steps=None):
+    """The modified SIR filter of Algorithm 6 for one run, over steps
+    t = 1..T (T = len(z) - 1 unless `steps` is given):
+      stage 1: predict + update (sir_predict_update);
+      stage 2: resample with B iterations (B = 0: B from eq. (bcalc) with
+               `epsilon`, per step), Philox key sir_step_seed(seed, t), stream
+               `run`, then x_bar = x[ancestors];
+      stage 3: the estimate, the mean of x_bar.
+    A step whose weights are all zero (fp32 underflow) keeps the predicted
+    particles unresampled (x_bar = x) and reports MGP_EWEIGHTS.
+    Returns (estimates[T], B[T], status[T], last x_bar)."""
+    xbar = np.ascontiguousarray(x0, dtype=np.float32)
+    T = len(z) - 1 if steps is None else steps
+    est, bs, sts = [], [], []
+    for t in range(1, T + 1):
+        x, w = sir_predict_update(xbar, t, float(z[t]), seed, run)
+        st = reduce(w)
+        if st.status:
+            xbar, b = x, 0
+        else:
+            b = B if B > 0 else choose_B(st.w_sum, st.w_max, w.size, epsilon)[0]
+            anc = resample(w, variant, b, sir_step_seed(seed, t), stream_id=run, partition_bytes=partition_bytes)
+            xbar = gather(x, anc).reshape(-1)
+        est.append(mean(xbar))
+        bs.append(b)
+        sts.append(st.status)
+    return np.array(est), np.array(bs, dtype=np.int64), np.array(sts, dtype=np.int64), xbar

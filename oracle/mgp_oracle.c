@@ -19,6 +19,7 @@
  *   - number of iterations B         : eq. (bcalc) in Section 3 and
  *                                      eq. (proposition), Section 4.1
  *   - particle copy x_bar_i = x_k    : last statement of Algorithms 2-5
+ *   - SIR application (predict, update, estimate): Algorithm 6, Section 7
  *
  * The paper fixes the algorithms but not the random-number generator (it used
  * a stateful generator on its GPU). Here every random draw is a pure function
@@ -35,6 +36,7 @@
  *   tag 2  Megopolis o_b  index = 0,          block = b / 4, word b % 4
  *   tag 3  C1 partition   index = group g,    block = 0,     word 0
  *   tag 4  C2 partition   index = group g,    block = b / 4, word b % 4
+ *   tag 5  SIR noise      index = particle i, block = step t, words 0, 1
  *
  * with group g = floor(i / 32) (the paper's warp index). Maps from 32-bit words:
  *   u in (0,1]   : m = 24 random bits, u = (m + 1) * 2^-24   (exact in fp32)
@@ -350,4 +352,55 @@ int mgp_oracle_gather(const float* states, int32_t n_states, int32_t d, const in
             out[(size_t)i * (size_t)d + (size_t)c] = states[(size_t)k * (size_t)d + (size_t)c];
     }
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The SIR application of Section 7 (Algorithm 6, eqs. (predict-end2end) and */
+/* (update-end2end)): x_t = x/2 + 25 x / (1 + x^2) + 8 cos(1.2 t) + v with    */
+/* v ~ N(0, 10); z_t = x_t^2 / 20 + n with n ~ N(0, 1); the unnormalised      */
+/* weight is the likelihood exp(-(z_t - x_t^2/20)^2 / 2).                     */
+/* ------------------------------------------------------------------------ */
+#define OR_TAG_SIR_NOISE 5u
+#define OR_PI 3.14159265358979323846
+
+/* Standard normal draw of particle i at step t of run `run`: Box-Muller on
+ * the first two words of Philox call (t, tag 5, run, i):
+ *   u1 = (x0 + 1) 2^-32 in (0, 1],  u2 = x1 2^-32 in [0, 1),
+ *   e  = sqrt(-2 ln u1) cos(2 pi u2)   (fp64). */
+double mgp_oracle_sir_normal(uint64_t seed, uint32_t run, uint32_t i, uint32_t t)
+{
+    uint32_t x[4];
+    draw_words(seed, OR_TAG_SIR_NOISE, run, i, t, x);
+    double u1 = ((double)x[0] + 1.0) * 0x1p-32;
+    double u2 = (double)x[1] * 0x1p-32;
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * OR_PI * u2);
+}
+
+/* Stage 1 of Algorithm 6 for n particles: predict from the resampled
+ * particles of step t-1 and weight by the measurement z_t. Arithmetic in
+ * fp64, each result rounded once to fp32. */
+void mgp_oracle_sir_predict_update(const float* xbar, int32_t n, uint32_t t, double z, uint64_t seed, uint32_t run,
+                                   float* x_out, float* w_out)
+{
+    const double sigma_v = sqrt(10.0);
+    const double drift = 8.0 * cos(1.2 * (double)t);
+    for (int32_t i = 0; i < n; ++i) {
+        double xp = (double)xbar[i];
+        double v = sigma_v * mgp_oracle_sir_normal(seed, run, (uint32_t)i, t);
+        double xn = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + drift + v;
+        float xf = (float)xn;
+        double xd = (double)xf;
+        double r = z - xd * xd / 20.0;
+        x_out[i] = xf;
+        w_out[i] = (float)exp(-0.5 * r * r);
+    }
+}
+
+/* Stage 3 of Algorithm 6: the estimate, the mean of the resampled particles
+ * (fp64, index order). */
+double mgp_oracle_mean(const float* x, int32_t n)
+{
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += (double)x[i];
+    return s / (double)n;
 }

@@ -91,3 +91,32 @@ def serving_requests(count: int, rate_per_s: float, n_lo_log2: float = 12.0, n_h
     y = g.uniform(0.0, 4.0, count)
     return t, n, y
 
+
+
+# ---------------------------------------------------------------------------
+# The SIR application's synthetic data (Section 7)
+# ---------------------------------------------------------------------------
+SIR_SEED = 2021
+
+
+def sir_truth(T: int = 100, trajectories: int = 16, seed: int = SIR_SEED):
+    """Ground-truth states x_0..x_T and measurements z_0..z_T of the model of
+    Section 7 (fp64): x_t = x_{t-1}/2 + 25 x_{t-1}/(1 + x_{t-1}^2) +
+    8 cos(1.2 t) + v, v ~ N(0, 10); z_t = x_t^2/20 + n, n ~ N(0, 1); x_0 ~ N(0, 5)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    x = np.empty((trajectories, T + 1))
+    z = np.empty((trajectories, T + 1))
+    x[:, 0] = g.normal(0.0, np.sqrt(5.0), trajectories)
+    z[:, 0] = x[:, 0] ** 2 / 20.0 + g.normal(0.0, 1.0, trajectories)
+    for t in range(1, T + 1):
+        xp = x[:, t - 1]
+        x[:, t] = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + 8.0 * np.cos(1.2 * t) + g.normal(0.0, np.sqrt(10.0),
+                                                                                             trajectories)
+        z[:, t] = x[:, t] ** 2 / 20.0 + g.normal(0.0, 1.0, trajectories)
+    return x, z
+
+
+def sir_initial_particles(n: int, run: int, seed: int = SIR_SEED + 1) -> np.ndarray:
+    """Initial particles of run `run`, drawn from the prior N(0, 5) (fp32)."""
+    g = np.random.Generator(np.random.PCG64(seed + 7919 * run))
+    return g.normal(0.0, np.sqrt(5.0), n).astype(np.float32)
