@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant sweep at N=2^22")
     ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--no-sir", action="store_true", help="skip the SIR filter section")
+    ap.add_argument("--sir-table", action="store_true",
+                    help="the SIR section for every (variant, B) row of Table 2 instead of Megopolis B=16 only")
+    ap.add_argument("--sir-mc-runs", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
     return ap.parse_args()
@@ -216,6 +220,94 @@ def sweep_section(torch, mgp, inputs):
             out.setdefault(key, {})[f"y{y}"] = {"ms": float(np.median(times)), "B": r.last_stats()["B"]}
     return {"workload": "N=2^22, Gaussian-likelihood weights, eps=0.01; resample = reduction + B + accept loop "
                         "(no gather); median of 5 runs", "ms": out}
+
+
+def table2():
+    """Table 2 of the paper (K40m): {(variant, B): (resample ratio, RMSE)}."""
+    with open(os.path.join(ROOT, "tests", "golden", "sir_table2.json")) as f:
+        g = json.load(f)
+    return {(r["variant"], r["B"]): (r["resample_ratio"], r["rmse"]) for r in g["rows"]}
+
+
+def sir_rmse(est, truth, trajectories, mc_runs):
+    """Mean over trajectories of the RMSE of Section 7: per step, the root
+    mean square error over the Monte Carlo runs; then the mean over steps."""
+    import numpy as np
+    T = est.shape[1]
+    e = est.reshape(trajectories, mc_runs, T) - truth[:, None, 1:]
+    per_traj = np.sqrt(np.mean(e * e, axis=1)).mean(axis=1)
+    return float(per_traj.mean()), per_traj
+
+
+def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20, T=100):
+    """Section 7's experiment: the SIR filter of Algorithm 6 on the model of
+    eqs. (predict-end2end)/(update-end2end), 16 ground-truth trajectories x
+    50 Monte Carlo runs, 2^20 particles, 100 steps, all 800 runs advanced
+    together. Per (variant, B): the whole experiment as one graph launch
+    (timed), then stage by stage with HIP events around each stage for the
+    resample ratio tau_2 / (tau_1 + tau_2 + tau_3), and the RMSE."""
+    import numpy as np
+    n = 1 << log2n
+    R = trajectories * mc_runs
+    dev = torch.device("cuda:0")
+    truth, z = inputs.sir_truth(T, trajectories)
+    zr = np.repeat(z, mc_runs, axis=0)  # run r follows trajectory r // mc_runs
+    x0 = inputs.sir_initial_particles_torch(R, n, dev)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for variant, B in rows:
+        key = f"{variant}-B{B}" if variant not in ("c1", "c2") else f"{variant}-ps128-B{B}"
+        t0 = time.perf_counter()
+        f = mgp.SirFilter(R, n, T, variant=variant, B=B, seed=2021, use_graph=True)
+        create_s = time.perf_counter() - t0
+        f.set_measurements(zr)
+        # the whole experiment, one graph launch (first launch warms up)
+        graph_ms = []
+        for rep in range(2):
+            f.reset(x0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            f.run()
+            b.record(stream)
+            torch.cuda.synchronize()
+            graph_ms.append(a.elapsed_time(b))
+        est, bs, st = f.results()
+        # stage by stage, events around each stage
+        f.reset(x0)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(T)]
+        for t in range(1, T + 1):
+            e = ev[t - 1]
+            e[0].record(stream)
+            f.predict_update(t)
+            e[1].record(stream)
+            f.resample(t)
+            e[2].record(stream)
+            f.estimate(t)
+            e[3].record(stream)
+        torch.cuda.synchronize()
+        tau = [sum(e[k].elapsed_time(e[k + 1]) for e in ev) for k in range(3)]
+        est2 = f.results()[0]
+        f.close()
+        rmse, per_traj = sir_rmse(est, truth, trajectories, mc_runs)
+        ratio = tau[1] / sum(tau)
+        paper = table2().get((variant, B))
+        steps = R * n * T
+        out[key] = {
+            "B": B, "rmse": rmse, "rmse_per_trajectory_min": float(per_traj.min()),
+            "rmse_per_trajectory_max": float(per_traj.max()),
+            "resample_ratio": ratio, "stage_ms_per_step": [x / T for x in tau],
+            "graph_ms_per_step": graph_ms[-1] / T, "particle_steps_per_s": steps / (graph_ms[-1] * 1e-3),
+            "stage_by_stage_equals_graph": bool(np.array_equal(est, est2)),
+            "degenerate_steps": int((st != 0).sum()), "create_s": create_s,
+            "paper_k40m": {"resample_ratio": paper[0], "rmse": paper[1]} if paper else None,
+        }
+        log(f"[bench] sir {key}: RMSE {rmse:.3f} (paper {paper[1] if paper else '-'}), ratio {ratio:.3f} "
+            f"(paper {paper[0] if paper else '-'}), stages {[round(x / T, 3) for x in tau]} ms/step, "
+            f"graph {graph_ms[-1] / T:.3f} ms/step")
+    del x0
+    return {"workload": f"SIR filter (Algorithm 6), {trajectories} trajectories x {mc_runs} Monte Carlo runs, "
+                        f"N=2^{log2n}, T={T}; stage 1 fp64, x/w fp32; C1/C2 partitions of 128 bytes",
+            "runs": R, "n": n, "steps": T, "rows": out}
 
 
 def serving_section(torch, mgp, inputs, n_requests, streams=4, max_batch=8, max_particles=1 << 22):
@@ -405,6 +497,13 @@ def main():
         sv = result["serving"]["budget_16GB"]
         log(f"[bench] serving: p50 {sv['p50_ms']:.3f} ms, p99 {sv['p99_ms']:.3f} ms, "
             f"{sv['particles_per_s']:.3e} particles/s")
+
+    if not args.no_sir:
+        rows = [("megopolis", 16)]
+        if args.sir_table:
+            rows = [(v, b) for b in (16, 32, 64) for v in ("megopolis", "metropolis", "c1", "c2")]
+        log(f"[bench] SIR filter: {len(rows)} configuration(s)")
+        result["sir"] = sir_section(torch, mgp, inputs, rows, mc_runs=args.sir_mc_runs)
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -296,6 +296,106 @@ int mgp_server_get_stats(mgp_server* server, mgp_server_stats* stats);
  * finish, frees everything. Outputs not yet released become invalid. */
 int mgp_server_destroy(mgp_server* server);
 
+/* ---- SIR particle filter ------------------------------------------------
+ * The modified SIR filter of Section 7 (Algorithm 6) on the model of eqs.
+ * (predict-end2end) and (update-end2end):
+ *   x_t = x_{t-1}/2 + 25 x_{t-1}/(1 + x_{t-1}^2) + 8 cos(1.2 t) + v,  v ~ N(0, 10)
+ *   z_t = x_t^2/20 + n,  n ~ N(0, 1)
+ * for R independent runs of n particles each, all runs advanced together:
+ *   stage 1  predict and update: x_t^(i) from x_bar_{t-1}^(i) and the noise,
+ *            w_t^(i) = exp(-(z_t - (x_t^(i))^2/20)^2 / 2) (the likelihood
+ *            without its constant factor; no normalisation);
+ *   stage 2  RESAMPLE: one batched resample of the R runs (mgp_batch_*
+ *            semantics, one filter per run, stream_id = run index), with the
+ *            fused gather x_bar_t^(i) = x_t^(k_i);
+ *   stage 3  the estimate x_hat_t = (sum_i x_bar_t^(i)) / n, in fp64.
+ * Arithmetic of stage 1 is fp64; x and w are stored as fp32. The noise of
+ * particle i, run r, step t is Box-Muller on words 0 and 1 of Philox4x32-10
+ * at counter (t, 5, r, i), key = seed:
+ *   u1 = (x0 + 1) 2^-32, u2 = x1 2^-32, v = sqrt(10) sqrt(-2 ln u1) cos(2 pi u2).
+ * The resample of step t uses key seed + t * 2^32 and stream r. A run whose
+ * weights all underflow to 0 at a step (status MGP_EWEIGHTS) keeps its
+ * predicted particles for that step (x_bar_t = x_t) and its estimate is their
+ * mean. Results are pure functions of (x_bar_0, z, config): identical for
+ * every launch shape and for graph or stage-by-stage execution, up to the
+ * ~1e-16 relative rounding order of the fp64 mean. */
+typedef struct mgp_sir_config {
+    int32_t variant;              /* mgp_variant of stage 2 */
+    int32_t runs;                 /* R, 1 <= R <= 65535 (e.g. trajectories x Monte Carlo runs) */
+    int32_t n;                    /* particles per run, 1 <= n <= 2^29 - 4096, R * n <= 2^32 */
+    int32_t steps;                /* T >= 1: the filter runs steps t = 1..T */
+    uint32_t B;                   /* > 0: iterations of every resample; 0: from epsilon at every step */
+    uint32_t partition_bytes;     /* C1/C2 partition size; 0 means 128 */
+    double epsilon;               /* bias bound in (0, 1], used when B == 0 (Section 7 uses 0.1) */
+    uint64_t seed;                /* Philox key of the noise; the resample of step t uses seed + t * 2^32 */
+    uint32_t b_max;               /* clamp / limit of B; 0 means 65536 */
+    int32_t use_graph;            /* 1: mgp_sir_run is one hipGraph launch of all T steps */
+    int32_t block_threads;        /* accept-loop block size (64, 128, 256); 0: 256 */
+    int32_t particles_per_thread; /* accept-loop particles per thread; 0: 4 for Megopolis, else 1 */
+    int32_t reserved;             /* must be 0 */
+    int32_t reserved2;            /* must be 0 */
+} mgp_sir_config;
+
+/* Device buffers of a filter, for inspection. Row r of each buffer starts at
+ * element r * ld; elements [0, n) of a row are used. */
+typedef struct mgp_sir_buffers {
+    float* x_dev;                 /* x_t: predicted particles of the last stage 1 */
+    float* w_dev;                 /* w_t: weights of the last stage 1 */
+    float* xbar_dev;              /* x_bar_t: particles after the last stage 2 */
+    int32_t* ancestors_dev;       /* ancestors of the last stage 2 */
+    int64_t ld;                   /* row stride in elements (n rounded up to 64) */
+    int64_t device_bytes;         /* device memory owned by the filter */
+    int64_t accept_grid;          /* workgroups of the stage-2 accept loop */
+    int32_t block_threads;
+    int32_t particles_per_thread;
+} mgp_sir_buffers;
+
+typedef struct mgp_sir_filter mgp_sir_filter;
+
+/* Allocates the filter's device memory (particles, weights, the per-run
+ * resampler tables, the estimate history) and, with use_graph, captures the T
+ * steps into one hipGraph. Measurements start as 0 (set them with
+ * mgp_sir_set_measurements); there are no particles until mgp_sir_reset.
+ * Synchronises `stream`. */
+int mgp_sir_create(const mgp_sir_config* config, void* stream, mgp_sir_filter** filter);
+
+/* z_host: R x (T + 1) fp64, row-major, host; z_host[r * (T + 1) + t] is the
+ * measurement of run r at step t (column 0 is unused). Copied before return. */
+int mgp_sir_set_measurements(mgp_sir_filter* filter, const double* z_host, void* stream);
+
+/* Starts over at step 1 from the initial particles x_bar_0: x0_dev is R x n
+ * fp32, row-major, device, copied on `stream`. Clears the history. */
+int mgp_sir_reset(mgp_sir_filter* filter, const float* x0_dev, void* stream);
+
+/* The three stages of step t (Algorithm 6), enqueued on `stream`. They must
+ * be called in the order stage 1, 2, 3 of step 1, then of step 2, ...;
+ * a call out of that order returns MGP_EINVAL and enqueues nothing. */
+int mgp_sir_predict_update(mgp_sir_filter* filter, int32_t t, void* stream);
+int mgp_sir_resample(mgp_sir_filter* filter, int32_t t, void* stream);
+int mgp_sir_estimate(mgp_sir_filter* filter, int32_t t, void* stream);
+
+/* Steps 1..T, right after mgp_sir_reset: one graph launch with use_graph,
+ * else 6 T plain launches. */
+int mgp_sir_run(mgp_sir_filter* filter, void* stream);
+
+/* Copies the history of the steps run so far (R x T each, row-major, host;
+ * entry [r * T + t - 1] is step t of run r; any pointer may be NULL):
+ * est_host the estimates x_hat_t, B_host the iterations of each resample,
+ * status_host MGP_OK or MGP_EWEIGHTS. Synchronises `stream`. */
+int mgp_sir_results(mgp_sir_filter* filter, double* est_host, uint32_t* B_host, int32_t* status_host, void* stream);
+
+int mgp_sir_get_buffers(const mgp_sir_filter* filter, mgp_sir_buffers* buffers);
+
+enum { MGP_SIR_X = 0, MGP_SIR_W = 1, MGP_SIR_XBAR = 2, MGP_SIR_ANCESTORS = 3 };
+
+/* Copies one buffer (MGP_SIR_X, _W, _XBAR: fp32; MGP_SIR_ANCESTORS: int32) as
+ * a dense R x n row-major array into dst_dev (device, caller-owned), on
+ * `stream`. */
+int mgp_sir_copy_buffer(const mgp_sir_filter* filter, int32_t which, void* dst_dev, void* stream);
+
+/* Frees the filter's device memory and graph. The filter must be idle. */
+int mgp_sir_destroy(mgp_sir_filter* filter);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* mgp_last_error(void);
 

@@ -1,0 +1,578 @@
+// mgp_sir.hip -- the modified SIR particle filter of Section 7 (Algorithm 6)
+// for many independent runs at once (gfx950).
+//
+// Model, eqs. (predict-end2end) and (update-end2end):
+//   x_t = x_{t-1}/2 + 25 x_{t-1} / (1 + x_{t-1}^2) + 8 cos(1.2 t) + v,  v ~ N(0, 10)
+//   z_t = x_t^2 / 20 + n,  n ~ N(0, 1)
+// and the weight of a particle is the likelihood p(z_t | x_t) without its
+// constant factor, exp(-(z_t - x_t^2/20)^2 / 2) (Algorithm 6 drops the
+// normalisation because the Metropolis-family resamplers do not need it).
+//
+// One step of R runs (one filter per run, each n particles) is:
+//   stage 1  k_sir_predict_update  one thread per particle of every run;
+//                                  fp64 arithmetic, x and w stored as fp32;
+//   stage 2  the batched resampler (segmented reduction + mirror, finalize,
+//            accept loop with the fused gather x_bar_i = x_{k_i}), one filter
+//            per run;
+//   stage 3  k_sir_mean_partial + k_sir_mean_final: x_hat_t = sum(x_bar) / n
+//            in fp64, in a fixed order that depends on n only.
+// The noise v of particle i in run r at step t is Box-Muller on the first two
+// words of Philox4x32-10 at counter (t, 5, r, i) under the filter's seed; the
+// resample of step t runs under key seed + t * 2^32 with stream r.
+//
+// A run whose weights all underflow to zero at some step (its resample
+// reports MGP_EWEIGHTS) keeps its predicted particles for that step: its
+// estimate is their mean and the next prediction starts from them.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mgp.h"
+#include "mgp_batch_internal.h"
+#include "mgp_device.h"
+#include "mgp_internal.h"
+#include "mgp_reduce.h"
+
+namespace mgp {
+
+constexpr uint32_t kTagSirNoise = 5u;
+constexpr uint32_t kSirThreads = 256;
+constexpr uint32_t kMeanChunk = 8192;  // particles per stage-3 partial sum
+constexpr uint32_t kRowAlign = 64;     // floats: every run's row starts 256-byte aligned
+constexpr double kPi = 3.14159265358979323846;
+
+// Stage 1 for particle i of run blockIdx.y.
+__global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float* __restrict__ xbar, float* x,
+                                                                    float* __restrict__ w,
+                                                                    const double* __restrict__ z,
+                                                                    const mgp_stats* __restrict__ stats,
+                                                                    FilterDev* __restrict__ fd, uint64_t ld,
+                                                                    uint32_t zld, uint32_t n, uint32_t t,
+                                                                    double drift, double sigma_v, uint32_t key0,
+                                                                    uint32_t key1)
+{
+    const uint32_t r = blockIdx.y;
+    const uint32_t i = blockIdx.x * kSirThreads + threadIdx.x;
+    // the resample of this step runs under key seed + t * 2^32
+    if (blockIdx.x == 0 && threadIdx.x == 0) fd[r].key1 = key1 + t;
+    if (i >= n) return;
+    const uint64_t at = (uint64_t)r * ld + i;
+    // a run whose last resample failed continues from its predicted particles
+    const double xp = stats[r].status == MGP_OK ? (double)xbar[at] : (double)x[at];
+    const Words q = philox(t, kTagSirNoise, r, i, key0, key1);
+    const double u1 = ((double)q.x0 + 1.0) * 0x1p-32;  // (0, 1]
+    const double u2 = (double)q.x1 * 0x1p-32;          // [0, 1)
+    const double e = sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+    const double v = sigma_v * e;
+    const double xn = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + drift + v;
+    const float xf = (float)xn;
+    const double xd = (double)xf;
+    const double res = z[(uint64_t)r * zld + t] - xd * xd / 20.0;
+    x[at] = xf;
+    w[at] = (float)exp(-0.5 * res * res);
+}
+
+// Stage 3, first pass: the fp64 sum of particles [c * kMeanChunk, ...) of run
+// blockIdx.y (of x_bar, or of x when that run's resample failed).
+template <bool Vec>
+__global__ __launch_bounds__(kReduceThreads) void k_sir_mean_partial(const float* __restrict__ xbar,
+                                                                     const float* __restrict__ x,
+                                                                     const mgp_stats* __restrict__ stats,
+                                                                     uint64_t ld, uint32_t n, uint32_t nchunks,
+                                                                     double* __restrict__ partial)
+{
+    const uint32_t r = blockIdx.y, c = blockIdx.x;
+    const float* src = (stats[r].status == MGP_OK ? xbar : x) + (uint64_t)r * ld;
+    const uint32_t start = c * kMeanChunk;
+    const uint32_t stop = min(n, start + kMeanChunk);
+    double s = 0.0;
+    uint32_t i = start + threadIdx.x;
+    if constexpr (Vec) {
+        const uint32_t stop4 = start + ((stop - start) & ~3u);
+        for (uint32_t j = start + 4u * threadIdx.x; j < stop4; j += 4u * kReduceThreads) {
+            const float4 v = *reinterpret_cast<const float4*>(src + j);
+            s += (double)v.x;
+            s += (double)v.y;
+            s += (double)v.z;
+            s += (double)v.w;
+        }
+        i = stop4 + threadIdx.x;
+    }
+    for (; i < stop; i += kReduceThreads) s += (double)src[i];
+    float mx = 0.0f;
+    uint32_t bad = 0;
+    block_reduce(mx, s, bad);
+    if (threadIdx.x == 0) partial[(uint64_t)r * nchunks + c] = s;
+}
+
+// Stage 3, second pass: x_hat_t = sum / n for run blockIdx.x, plus the B and
+// status of that run's resample at step t.
+__global__ __launch_bounds__(kReduceThreads) void k_sir_mean_final(const double* __restrict__ partial,
+                                                                   uint32_t nchunks, uint32_t n,
+                                                                   const mgp_stats* __restrict__ stats,
+                                                                   double* __restrict__ est,
+                                                                   uint32_t* __restrict__ b_hist,
+                                                                   int32_t* __restrict__ st_hist, uint32_t T,
+                                                                   uint32_t t)
+{
+    const uint32_t r = blockIdx.x;
+    double s = 0.0;
+    for (uint32_t c = threadIdx.x; c < nchunks; c += kReduceThreads) s += partial[(uint64_t)r * nchunks + c];
+    float mx = 0.0f;
+    uint32_t bad = 0;
+    block_reduce(mx, s, bad);
+    if (threadIdx.x == 0) {
+        const uint64_t at = (uint64_t)r * T + (t - 1);
+        est[at] = s / (double)n;
+        b_hist[at] = stats[r].B;
+        st_hist[at] = stats[r].status;
+    }
+}
+
+}  // namespace mgp
+
+// ---------------------------------------------------------------------------
+// Filter object
+// ---------------------------------------------------------------------------
+using namespace mgp;
+
+struct mgp_sir_filter {
+    mgp_sir_config cfg{};
+    int device = 0;
+    int nxcd = 1;
+    uint32_t n = 0, R = 0, T = 0;
+    uint64_t ld = 0;          // row stride (floats) of x, w, x_bar, ancestors
+    uint32_t nchunks = 0;     // stage-3 partials per run
+    uint32_t zld = 0;         // T + 1
+    uint32_t key0 = 0, key1 = 0;
+    double sigma_v = 0.0;
+    LoopShape shape{256, 4, 1};
+    char* dmem = nullptr;
+    size_t dmem_bytes = 0;
+    float *x = nullptr, *w = nullptr, *xbar = nullptr;
+    int32_t* anc = nullptr;
+    double* z = nullptr;
+    double* est = nullptr;
+    uint32_t* b_hist = nullptr;
+    int32_t* st_hist = nullptr;
+    double* mean_part = nullptr;
+    FilterDev* d_fd = nullptr;
+    RTile* d_rt = nullptr;
+    uint32_t n_rt = 0;
+    Partial* d_parts = nullptr;
+    mgp_stats* d_stats = nullptr;
+    uint32_t* d_qcount = nullptr;
+    uint32_t* d_qoff = nullptr;
+    LTile* d_lt = nullptr;
+    uint32_t grid = 0;
+    // host-side order of the stages: step next_t, stage next_stage (1..3);
+    // next_t == 0 until the first reset
+    uint32_t next_t = 0;
+    int next_stage = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+#define HIP_TRY(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail(MGP_EHIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
+
+int validate(const mgp_sir_config* c)
+{
+    if (!c) return fail(MGP_EINVAL, "config is NULL");
+    if (c->variant < MGP_METROPOLIS || c->variant > MGP_MEGOPOLIS) return fail(MGP_EINVAL, "unknown variant %d", c->variant);
+    if (c->runs < 1 || c->runs > 65535) return fail(MGP_ERANGE, "runs = %d outside [1, 65535]", c->runs);
+    if (c->n < 1 || (uint32_t)c->n > kBatchMaxN) return fail(MGP_ERANGE, "n = %d out of range", c->n);
+    if ((uint64_t)c->runs * (uint64_t)c->n > (1ull << 32)) return fail(MGP_ERANGE, "runs * n above 2^32");
+    if (c->steps < 1) return fail(MGP_EINVAL, "steps must be >= 1");
+    const uint32_t pb = c->partition_bytes ? c->partition_bytes : 128u;
+    if (pb < 4u || pb % 4u) return fail(MGP_EINVAL, "partition_bytes must be a positive multiple of 4");
+    const uint32_t bmax = c->b_max ? c->b_max : kDefaultBMax;
+    if (bmax > kBMaxLimit) return fail(MGP_ERANGE, "b_max above %u", kBMaxLimit);
+    if (c->B == 0 && (!(c->epsilon > 0.0) || !(c->epsilon <= 1.0)))
+        return fail(MGP_EINVAL, "epsilon must be in (0, 1] when B is 0");
+    if (c->B > bmax) return fail(MGP_ERANGE, "B = %u above b_max = %u", c->B, bmax);
+    if (c->reserved || c->reserved2) return fail(MGP_EINVAL, "reserved must be 0");
+    if (c->block_threads || c->particles_per_thread) {
+        const LoopShape want{c->block_threads ? c->block_threads : 256,
+                             c->particles_per_thread ? c->particles_per_thread : (c->variant == MGP_MEGOPOLIS ? 4 : 1),
+                             1};
+        if (!batch_shape_supported(c->variant, want))
+            return fail(MGP_EINVAL, "unsupported launch shape bt=%d ppt=%d", want.bt, want.ppt);
+    }
+    return MGP_OK;
+}
+
+int check_stage(mgp_sir_filter* f, int32_t t, int stage)
+{
+    if (f->next_t == 0) return fail(MGP_EINVAL, "the filter has no particles: call mgp_sir_reset first");
+    if (t < 1 || (uint32_t)t > f->T) return fail(MGP_ERANGE, "step %d outside [1, %u]", t, f->T);
+    if ((uint32_t)t != f->next_t || stage != f->next_stage)
+        return fail(MGP_EINVAL, "out of order: step %d stage %d called, step %u stage %d expected", t, stage, f->next_t,
+                    f->next_stage);
+    return MGP_OK;
+}
+
+void advance(mgp_sir_filter* f)
+{
+    if (++f->next_stage > 3) {
+        f->next_stage = 1;
+        ++f->next_t;
+    }
+}
+
+int enqueue_predict(mgp_sir_filter* f, uint32_t t, hipStream_t s)
+{
+    const double drift = 8.0 * cos(1.2 * (double)t);
+    const dim3 grid((f->n + kSirThreads - 1) / kSirThreads, f->R);
+    hipLaunchKernelGGL(k_sir_predict_update, grid, dim3(kSirThreads), 0, s, f->xbar, f->x, f->w, f->z, f->d_stats,
+                       f->d_fd, f->ld, f->zld, f->n, t, drift, f->sigma_v, f->key0, f->key1);
+    return check_launch("SIR predict/update");
+}
+
+int enqueue_resample(mgp_sir_filter* f, hipStream_t s)
+{
+    return enqueue_batch(f->cfg.variant, f->shape, f->d_fd, f->R, f->d_rt, f->n_rt, f->d_parts, f->d_stats, f->d_lt,
+                         f->grid, f->d_qoff, f->d_qcount, (uint32_t)f->nxcd, 1u, s);
+}
+
+int enqueue_estimate(mgp_sir_filter* f, uint32_t t, hipStream_t s)
+{
+    const dim3 grid(f->nchunks, f->R);
+    if (f->ld % 4u == 0)
+        hipLaunchKernelGGL(k_sir_mean_partial<true>, grid, dim3(kReduceThreads), 0, s, f->xbar, f->x, f->d_stats, f->ld,
+                           f->n, f->nchunks, f->mean_part);
+    else
+        hipLaunchKernelGGL(k_sir_mean_partial<false>, grid, dim3(kReduceThreads), 0, s, f->xbar, f->x, f->d_stats,
+                           f->ld, f->n, f->nchunks, f->mean_part);
+    int rc = check_launch("SIR mean (partial sums)");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sir_mean_final, dim3(f->R), dim3(kReduceThreads), 0, s, f->mean_part, f->nchunks, f->n,
+                       f->d_stats, f->est, f->b_hist, f->st_hist, f->T, t);
+    return check_launch("SIR mean (final)");
+}
+
+int enqueue_steps(mgp_sir_filter* f, hipStream_t s)
+{
+    for (uint32_t t = 1; t <= f->T; ++t) {
+        int rc = enqueue_predict(f, t, s);
+        if (!rc) rc = enqueue_resample(f, s);
+        if (!rc) rc = enqueue_estimate(f, t, s);
+        if (rc) return rc;
+    }
+    return MGP_OK;
+}
+
+int capture(mgp_sir_filter* f)
+{
+    HIP_TRY(hipStreamBeginCapture(f->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_steps(f, f->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(f->capture_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(MGP_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    f->graph = g;
+    HIP_TRY(hipGraphInstantiate(&f->exec, f->graph, nullptr, nullptr, 0));
+    return MGP_OK;
+}
+
+void free_filter(mgp_sir_filter* f)
+{
+    if (!f) return;
+    // best-effort teardown: a failure here leaves nothing to recover
+    if (f->exec) (void)hipGraphExecDestroy(f->exec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
+    if (f->capture_stream) (void)hipStreamDestroy(f->capture_stream);
+    if (f->dmem) (void)hipFree(f->dmem);
+    delete f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out)
+{
+    clear_error();
+    if (!out) return fail(MGP_EINVAL, "filter pointer is NULL");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mgp_sir_filter* f = new mgp_sir_filter();
+    auto bail = [&](int code) {
+        free_filter(f);
+        return code;
+    };
+    f->cfg = *cfg;
+    f->cfg.partition_bytes = cfg->partition_bytes ? cfg->partition_bytes : 128u;
+    f->cfg.b_max = cfg->b_max ? cfg->b_max : kDefaultBMax;
+    f->n = (uint32_t)cfg->n;
+    f->R = (uint32_t)cfg->runs;
+    f->T = (uint32_t)cfg->steps;
+    f->zld = f->T + 1;
+    f->ld = ((uint64_t)f->n + kRowAlign - 1) / kRowAlign * kRowAlign;
+    f->nchunks = (f->n + kMeanChunk - 1) / kMeanChunk;
+    f->key0 = (uint32_t)cfg->seed;
+    f->key1 = (uint32_t)(cfg->seed >> 32);
+    f->sigma_v = sqrt(10.0);
+    const bool mego = cfg->variant == MGP_MEGOPOLIS;
+    f->shape = LoopShape{cfg->block_threads ? cfg->block_threads : 256,
+                         cfg->particles_per_thread ? cfg->particles_per_thread : (mego ? 4 : 1), 1};
+    if (hipGetDevice(&f->device) != hipSuccess) return bail(fail(MGP_EHIP, "hipGetDevice failed"));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, f->device) != hipSuccess)
+        return bail(fail(MGP_EHIP, "hipGetDeviceProperties failed"));
+    f->nxcd = (prop.multiProcessorCount >= 64 && prop.multiProcessorCount % kMaxXcd == 0) ? kMaxXcd : 1;
+
+    // ---- accept-loop tiles: R equal filters, XCD-balanced
+    const uint32_t B_fixed = cfg->B;
+    std::vector<uint32_t> ns(f->R, f->n);
+    std::vector<double> cost(f->R, (double)f->n * std::max<uint32_t>(1u, B_fixed ? B_fixed : 32u));
+    std::vector<LTile> table;
+    std::vector<uint32_t> qoff(kMaxXcd + 1, 0);
+    build_tile_table(ns, cost, f->shape, f->nxcd, table, qoff.data());
+    if (table.empty()) table.push_back(LTile{kNoFilter, 0});
+    f->grid = (uint32_t)table.size();
+
+    // ---- one allocation: particles, weights, histories, resampler tables
+    const uint32_t nparts = reduce_blocks(f->n);
+    const uint32_t chunk = reduce_chunk(f->n, nparts);
+    f->n_rt = nparts * f->R;
+    const uint32_t offs_cap = B_fixed ? B_fixed : f->cfg.b_max;
+    const size_t rows = (size_t)f->R * f->ld;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const size_t o_x = take(rows * sizeof(float));
+    const size_t o_w = take(rows * sizeof(float));
+    const size_t o_xbar = take(rows * sizeof(float));
+    const size_t o_anc = take(rows * sizeof(int32_t));
+    const size_t o_z = take((size_t)f->R * f->zld * sizeof(double));
+    const size_t o_est = take((size_t)f->R * f->T * sizeof(double));
+    const size_t o_bh = take((size_t)f->R * f->T * sizeof(uint32_t));
+    const size_t o_sh = take((size_t)f->R * f->T * sizeof(int32_t));
+    const size_t o_mp = take((size_t)f->R * f->nchunks * sizeof(double));
+    const size_t o_fd = take((size_t)f->R * sizeof(FilterDev));
+    const size_t o_rt = take((size_t)f->n_rt * sizeof(RTile));
+    const size_t o_parts = take((size_t)f->n_rt * sizeof(Partial));
+    const size_t o_stats = take((size_t)f->R * sizeof(mgp_stats));
+    const size_t o_q = take(sizeof(uint32_t) * 2 * (kMaxXcd + 1));
+    const size_t o_lt = take(table.size() * sizeof(LTile));
+    const size_t mirror_row = align256(sizeof(float) * (2 * (size_t)f->n + kMirrorPad));
+    const size_t offs_row = align256(sizeof(uint32_t) * (size_t)offs_cap);
+    const size_t o_offs = mego ? take((size_t)f->R * offs_row) : 0;
+    const size_t o_mirror = mego ? take((size_t)f->R * mirror_row) : 0;
+    f->dmem_bytes = off;
+    if (hipMalloc(&f->dmem, f->dmem_bytes) != hipSuccess)
+        return bail(fail(MGP_ENOMEM, "could not allocate %zu bytes for the filter", f->dmem_bytes));
+    f->x = reinterpret_cast<float*>(f->dmem + o_x);
+    f->w = reinterpret_cast<float*>(f->dmem + o_w);
+    f->xbar = reinterpret_cast<float*>(f->dmem + o_xbar);
+    f->anc = reinterpret_cast<int32_t*>(f->dmem + o_anc);
+    f->z = reinterpret_cast<double*>(f->dmem + o_z);
+    f->est = reinterpret_cast<double*>(f->dmem + o_est);
+    f->b_hist = reinterpret_cast<uint32_t*>(f->dmem + o_bh);
+    f->st_hist = reinterpret_cast<int32_t*>(f->dmem + o_sh);
+    f->mean_part = reinterpret_cast<double*>(f->dmem + o_mp);
+    f->d_fd = reinterpret_cast<FilterDev*>(f->dmem + o_fd);
+    f->d_rt = reinterpret_cast<RTile*>(f->dmem + o_rt);
+    f->d_parts = reinterpret_cast<Partial*>(f->dmem + o_parts);
+    f->d_stats = reinterpret_cast<mgp_stats*>(f->dmem + o_stats);
+    f->d_qcount = reinterpret_cast<uint32_t*>(f->dmem + o_q);
+    f->d_qoff = f->d_qcount + (kMaxXcd + 1);
+    f->d_lt = reinterpret_cast<LTile*>(f->dmem + o_lt);
+
+    std::vector<FilterDev> fd(f->R);
+    std::vector<RTile> rt;
+    rt.reserve(f->n_rt);
+    const uint32_t n_w = f->cfg.partition_bytes / 4u;
+    for (uint32_t r = 0; r < f->R; ++r) {
+        FilterDev& F = fd[r];
+        memset(&F, 0, sizeof F);
+        F.w = f->w + (size_t)r * f->ld;
+        F.anc = f->anc + (size_t)r * f->ld;
+        F.states = f->x + (size_t)r * f->ld;
+        F.out = f->xbar + (size_t)r * f->ld;
+        F.stats_user = nullptr;
+        F.mirror = mego ? reinterpret_cast<float*>(f->dmem + o_mirror + (size_t)r * mirror_row) : nullptr;
+        F.offsets = mego ? reinterpret_cast<uint32_t*>(f->dmem + o_offs + (size_t)r * offs_row) : nullptr;
+        F.eps = cfg->epsilon;
+        F.n = f->n;
+        F.B_user = B_fixed;
+        F.b_max = f->cfg.b_max;
+        F.key0 = f->key0;
+        F.key1 = f->key1;  // replaced by key1 + t at every step
+        F.stream_id = r;
+        F.part_base = r * nparts;
+        F.nparts = nparts;
+        F.chunk = chunk;
+        F.n_w = n_w;
+        F.n_part = (uint32_t)(((uint64_t)f->n + n_w - 1u) / n_w);
+        F.vec = (!mego || f->n % 4u == 0) ? 1u : 0u;  // rows are 256-byte aligned
+        F.rows4 = 0;
+        for (uint32_t c = 0; c < nparts; ++c) rt.push_back(RTile{r, c});
+    }
+    if (hipMemcpyAsync(f->d_fd, fd.data(), fd.size() * sizeof(FilterDev), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f->d_rt, rt.data(), rt.size() * sizeof(RTile), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f->d_lt, table.data(), table.size() * sizeof(LTile), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f->d_qoff, qoff.data(), qoff.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(f->z, 0, (size_t)f->R * f->zld * sizeof(double), s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(MGP_EHIP, "uploading the filter tables failed"));
+    if (hipStreamCreateWithFlags(&f->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(MGP_EHIP, "hipStreamCreate failed"));
+    if (cfg->use_graph) {
+        rc = capture(f);
+        if (rc) return bail(rc);
+    }
+    *out = f;
+    return MGP_OK;
+}
+
+int mgp_sir_set_measurements(mgp_sir_filter* f, const double* z_host, void* stream)
+{
+    clear_error();
+    if (!f || !z_host) return fail(MGP_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(f->z, z_host, (size_t)f->R * f->zld * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MGP_OK;
+}
+
+int mgp_sir_reset(mgp_sir_filter* f, const float* x0_dev, void* stream)
+{
+    clear_error();
+    if (!f || !x0_dev) return fail(MGP_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpy2DAsync(f->xbar, f->ld * sizeof(float), x0_dev, (size_t)f->n * sizeof(float),
+                             (size_t)f->n * sizeof(float), f->R, hipMemcpyDeviceToDevice, s));
+    // status MGP_OK for every run: step 1 predicts from x_bar_0
+    HIP_TRY(hipMemsetAsync(f->d_stats, 0, (size_t)f->R * sizeof(mgp_stats), s));
+    HIP_TRY(hipMemsetAsync(f->est, 0, (size_t)f->R * f->T * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(f->b_hist, 0, (size_t)f->R * f->T * sizeof(uint32_t), s));
+    HIP_TRY(hipMemsetAsync(f->st_hist, 0, (size_t)f->R * f->T * sizeof(int32_t), s));
+    f->next_t = 1;
+    f->next_stage = 1;
+    return MGP_OK;
+}
+
+int mgp_sir_predict_update(mgp_sir_filter* f, int32_t t, void* stream)
+{
+    clear_error();
+    if (!f) return fail(MGP_EINVAL, "filter is NULL");
+    int rc = check_stage(f, t, 1);
+    if (!rc) rc = enqueue_predict(f, (uint32_t)t, static_cast<hipStream_t>(stream));
+    if (!rc) advance(f);
+    return rc;
+}
+
+int mgp_sir_resample(mgp_sir_filter* f, int32_t t, void* stream)
+{
+    clear_error();
+    if (!f) return fail(MGP_EINVAL, "filter is NULL");
+    int rc = check_stage(f, t, 2);
+    if (!rc) rc = enqueue_resample(f, static_cast<hipStream_t>(stream));
+    if (!rc) advance(f);
+    return rc;
+}
+
+int mgp_sir_estimate(mgp_sir_filter* f, int32_t t, void* stream)
+{
+    clear_error();
+    if (!f) return fail(MGP_EINVAL, "filter is NULL");
+    int rc = check_stage(f, t, 3);
+    if (!rc) rc = enqueue_estimate(f, (uint32_t)t, static_cast<hipStream_t>(stream));
+    if (!rc) advance(f);
+    return rc;
+}
+
+int mgp_sir_run(mgp_sir_filter* f, void* stream)
+{
+    clear_error();
+    if (!f) return fail(MGP_EINVAL, "filter is NULL");
+    int rc = check_stage(f, 1, 1);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (f->exec) {
+        HIP_TRY(hipGraphLaunch(f->exec, s));
+    } else {
+        rc = enqueue_steps(f, s);
+        if (rc) return rc;
+    }
+    f->next_t = f->T + 1;
+    f->next_stage = 1;
+    return MGP_OK;
+}
+
+int mgp_sir_results(mgp_sir_filter* f, double* est_host, uint32_t* B_host, int32_t* status_host, void* stream)
+{
+    clear_error();
+    if (!f) return fail(MGP_EINVAL, "filter is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t cnt = (size_t)f->R * f->T;
+    if (est_host) HIP_TRY(hipMemcpyAsync(est_host, f->est, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (B_host) HIP_TRY(hipMemcpyAsync(B_host, f->b_hist, cnt * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (status_host) HIP_TRY(hipMemcpyAsync(status_host, f->st_hist, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MGP_OK;
+}
+
+int mgp_sir_get_buffers(const mgp_sir_filter* f, mgp_sir_buffers* b)
+{
+    clear_error();
+    if (!f || !b) return fail(MGP_EINVAL, "NULL argument");
+    b->x_dev = f->x;
+    b->w_dev = f->w;
+    b->xbar_dev = f->xbar;
+    b->ancestors_dev = f->anc;
+    b->ld = (int64_t)f->ld;
+    b->device_bytes = (int64_t)f->dmem_bytes;
+    b->accept_grid = (int64_t)f->grid;
+    b->block_threads = f->shape.bt;
+    b->particles_per_thread = f->shape.ppt;
+    return MGP_OK;
+}
+
+int mgp_sir_copy_buffer(const mgp_sir_filter* f, int32_t which, void* dst_dev, void* stream)
+{
+    clear_error();
+    if (!f || !dst_dev) return fail(MGP_EINVAL, "NULL argument");
+    const void* src = which == MGP_SIR_X      ? (const void*)f->x
+                      : which == MGP_SIR_W    ? (const void*)f->w
+                      : which == MGP_SIR_XBAR ? (const void*)f->xbar
+                      : which == MGP_SIR_ANCESTORS ? (const void*)f->anc
+                                                   : nullptr;
+    if (!src) return fail(MGP_EINVAL, "unknown buffer %d", which);
+    HIP_TRY(hipMemcpy2DAsync(dst_dev, (size_t)f->n * 4u, src, f->ld * 4u, (size_t)f->n * 4u, f->R,
+                             hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+    return MGP_OK;
+}
+
+int mgp_sir_destroy(mgp_sir_filter* f)
+{
+    clear_error();
+    if (!f) return MGP_OK;
+    free_filter(f);
+    return MGP_OK;
+}
+
+}  // extern "C"

@@ -120,3 +120,14 @@ def sir_initial_particles(n: int, run: int, seed: int = SIR_SEED + 1) -> np.ndar
     """Initial particles of run `run`, drawn from the prior N(0, 5) (fp32)."""
     g = np.random.Generator(np.random.PCG64(seed + 7919 * run))
     return g.normal(0.0, np.sqrt(5.0), n).astype(np.float32)
+
+
+def sir_initial_particles_torch(runs: int, n: int, device, seed: int = SIR_SEED + 2):
+    """Initial particles of `runs` runs drawn from the prior N(0, 5) by torch's
+    seeded generator on `device` (fp32, [runs, n]): for experiments too large
+    to draw on the host."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    x = torch.randn((runs, n), generator=g, device=device, dtype=torch.float32)
+    return x.mul_(float(np.sqrt(5.0)))

@@ -91,6 +91,22 @@ class mgp_server_stats(ctypes.Structure):
                 ("max_concurrent_batches", ctypes.c_int64)]
 
 
+class mgp_sir_config(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("runs", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("B", ctypes.c_uint32), ("partition_bytes", ctypes.c_uint32),
+                ("epsilon", ctypes.c_double), ("seed", ctypes.c_uint64), ("b_max", ctypes.c_uint32),
+                ("use_graph", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("particles_per_thread", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
+
+
+class mgp_sir_buffers(ctypes.Structure):
+    _fields_ = [("x_dev", ctypes.c_void_p), ("w_dev", ctypes.c_void_p), ("xbar_dev", ctypes.c_void_p),
+                ("ancestors_dev", ctypes.c_void_p), ("ld", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("accept_grid", ctypes.c_int64), ("block_threads", ctypes.c_int32),
+                ("particles_per_thread", ctypes.c_int32)]
+
+
 MGP_REQ_QUEUED, MGP_REQ_RUNNING, MGP_REQ_DONE, MGP_REQ_FAILED, MGP_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 STATS_BYTES = ctypes.sizeof(mgp_stats)
@@ -137,6 +153,21 @@ def lib():
         L.mgp_server_destroy.argtypes = [_vp]
         for f in ("mgp_server_create", "mgp_server_submit", "mgp_server_poll", "mgp_server_wait", "mgp_server_cancel",
                   "mgp_server_copy_outputs", "mgp_server_release", "mgp_server_get_stats", "mgp_server_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        L.mgp_sir_create.argtypes = [ctypes.POINTER(mgp_sir_config), _vp, ctypes.POINTER(_vp)]
+        L.mgp_sir_set_measurements.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _vp]
+        L.mgp_sir_reset.argtypes = [_vp, _vp, _vp]
+        L.mgp_sir_predict_update.argtypes = [_vp, ctypes.c_int32, _vp]
+        L.mgp_sir_resample.argtypes = [_vp, ctypes.c_int32, _vp]
+        L.mgp_sir_estimate.argtypes = [_vp, ctypes.c_int32, _vp]
+        L.mgp_sir_run.argtypes = [_vp, _vp]
+        L.mgp_sir_results.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.mgp_sir_get_buffers.argtypes = [_vp, ctypes.POINTER(mgp_sir_buffers)]
+        L.mgp_sir_destroy.argtypes = [_vp]
+        L.mgp_sir_copy_buffer.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+        for f in ("mgp_sir_copy_buffer", "mgp_sir_create", "mgp_sir_set_measurements", "mgp_sir_reset", "mgp_sir_predict_update",
+                  "mgp_sir_resample", "mgp_sir_estimate", "mgp_sir_run", "mgp_sir_results", "mgp_sir_get_buffers",
+                  "mgp_sir_destroy"):
             getattr(L, f).restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
@@ -282,6 +313,62 @@ def mgp_server_get_stats(server: int) -> dict:
 
 def mgp_server_destroy(server: int) -> None:
     _check(lib().mgp_server_destroy(server), "mgp_server_destroy")
+
+
+def mgp_sir_create(config: mgp_sir_config, stream: int) -> int:
+    h = _vp()
+    _check(lib().mgp_sir_create(ctypes.byref(config), stream or None, ctypes.byref(h)), "mgp_sir_create")
+    return h.value
+
+
+def mgp_sir_set_measurements(filt: int, z: np.ndarray, stream: int) -> None:
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    _check(lib().mgp_sir_set_measurements(filt, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), stream or None),
+           "mgp_sir_set_measurements")
+
+
+def mgp_sir_reset(filt: int, x0_dev: int, stream: int) -> None:
+    _check(lib().mgp_sir_reset(filt, x0_dev, stream or None), "mgp_sir_reset")
+
+
+def mgp_sir_predict_update(filt: int, t: int, stream: int) -> None:
+    _check(lib().mgp_sir_predict_update(filt, t, stream or None), "mgp_sir_predict_update")
+
+
+def mgp_sir_resample(filt: int, t: int, stream: int) -> None:
+    _check(lib().mgp_sir_resample(filt, t, stream or None), "mgp_sir_resample")
+
+
+def mgp_sir_estimate(filt: int, t: int, stream: int) -> None:
+    _check(lib().mgp_sir_estimate(filt, t, stream or None), "mgp_sir_estimate")
+
+
+def mgp_sir_run(filt: int, stream: int) -> None:
+    _check(lib().mgp_sir_run(filt, stream or None), "mgp_sir_run")
+
+
+def mgp_sir_results(filt: int, est: np.ndarray | None, B: np.ndarray | None, status: np.ndarray | None,
+                    stream: int) -> None:
+    def ptr(a):
+        return None if a is None else a.ctypes.data
+    _check(lib().mgp_sir_results(filt, ptr(est), ptr(B), ptr(status), stream or None), "mgp_sir_results")
+
+
+def mgp_sir_get_buffers(filt: int) -> dict:
+    b = mgp_sir_buffers()
+    _check(lib().mgp_sir_get_buffers(filt, ctypes.byref(b)), "mgp_sir_get_buffers")
+    return {k: getattr(b, k) for k, _ in mgp_sir_buffers._fields_}
+
+
+MGP_SIR_X, MGP_SIR_W, MGP_SIR_XBAR, MGP_SIR_ANCESTORS = 0, 1, 2, 3
+
+
+def mgp_sir_copy_buffer(filt: int, which: int, dst_dev: int, stream: int) -> None:
+    _check(lib().mgp_sir_copy_buffer(filt, which, dst_dev, stream or None), "mgp_sir_copy_buffer")
+
+
+def mgp_sir_destroy(filt: int) -> None:
+    _check(lib().mgp_sir_destroy(filt), "mgp_sir_destroy")
 
 
 # ---------------------------------------------------------------------------
@@ -487,6 +574,87 @@ class Server:
         if self.handle:
             mgp_server_destroy(self.handle)
             self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SirFilter:
+    """Owns an mgp_sir_filter: R runs of the SIR filter of Algorithm 6, n
+    particles each, T steps, stage 2 done by `variant` with B iterations (or B
+    from epsilon per step when B is 0)."""
+
+    def __init__(self, runs: int, n: int, steps: int, variant="megopolis", B: int = 16, epsilon: float = 0.1,
+                 seed: int = 0, partition_bytes: int = 128, b_max: int = 0, use_graph: bool = True,
+                 block_threads: int = 0, particles_per_thread: int = 0, stream: int | None = None):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        cfg = mgp_sir_config(v, int(runs), int(n), int(steps), int(B), int(partition_bytes), float(epsilon),
+                             int(seed) & (2**64 - 1), int(b_max), 1 if use_graph else 0, int(block_threads),
+                             int(particles_per_thread), 0, 0)
+        self.runs, self.n, self.steps = int(runs), int(n), int(steps)
+        self.filt = mgp_sir_create(cfg, current_stream() if stream is None else stream)
+
+    def _s(self, stream):
+        return current_stream() if stream is None else stream
+
+    def set_measurements(self, z, stream: int | None = None) -> None:
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        if z.shape != (self.runs, self.steps + 1):
+            raise ValueError(f"measurements must have shape ({self.runs}, {self.steps + 1})")
+        mgp_sir_set_measurements(self.filt, z, self._s(stream))
+
+    def reset(self, x0, stream: int | None = None) -> None:
+        torch = _torch()
+        if (x0.dtype != torch.float32 or not x0.is_cuda or not x0.is_contiguous()
+                or tuple(x0.shape) != (self.runs, self.n)):
+            raise ValueError(f"initial particles must be a contiguous fp32 device tensor of shape "
+                             f"({self.runs}, {self.n})")
+        mgp_sir_reset(self.filt, x0.data_ptr(), self._s(stream))
+
+    def predict_update(self, t: int, stream: int | None = None) -> None:
+        mgp_sir_predict_update(self.filt, t, self._s(stream))
+
+    def resample(self, t: int, stream: int | None = None) -> None:
+        mgp_sir_resample(self.filt, t, self._s(stream))
+
+    def estimate(self, t: int, stream: int | None = None) -> None:
+        mgp_sir_estimate(self.filt, t, self._s(stream))
+
+    def step(self, t: int, stream: int | None = None) -> None:
+        self.predict_update(t, stream)
+        self.resample(t, stream)
+        self.estimate(t, stream)
+
+    def run(self, stream: int | None = None) -> None:
+        mgp_sir_run(self.filt, self._s(stream))
+
+    def results(self, stream: int | None = None):
+        """(estimates [R, T] fp64, B [R, T] uint32, status [R, T] int32)."""
+        est = np.zeros((self.runs, self.steps), dtype=np.float64)
+        B = np.zeros((self.runs, self.steps), dtype=np.uint32)
+        st = np.zeros((self.runs, self.steps), dtype=np.int32)
+        mgp_sir_results(self.filt, est, B, st, self._s(stream))
+        return est, B, st
+
+    def buffers(self) -> dict:
+        return mgp_sir_get_buffers(self.filt)
+
+    def copy(self, name: str, stream: int | None = None):
+        """A new device tensor [R, n] holding 'x', 'w', 'xbar' (fp32) or 'ancestors' (int32)."""
+        torch = _torch()
+        which = {"x": MGP_SIR_X, "w": MGP_SIR_W, "xbar": MGP_SIR_XBAR, "ancestors": MGP_SIR_ANCESTORS}[name]
+        out = torch.empty((self.runs, self.n), dtype=torch.int32 if name == "ancestors" else torch.float32,
+                          device="cuda")
+        mgp_sir_copy_buffer(self.filt, which, out.data_ptr(), self._s(stream))
+        return out
+
+    def close(self) -> None:
+        if self.filt:
+            mgp_sir_destroy(self.filt)
+            self.filt = 0
 
     def __del__(self):
         try:

@@ -42,6 +42,14 @@ int main(void)
     F(mgp_server_stats, released); F(mgp_server_stats, micro_batches); F(mgp_server_stats, queued);
     F(mgp_server_stats, in_flight); F(mgp_server_stats, pool_bytes); F(mgp_server_stats, pool_in_use);
     F(mgp_server_stats, pool_peak); F(mgp_server_stats, max_concurrent_batches);
+    S(mgp_sir_config); F(mgp_sir_config, variant); F(mgp_sir_config, runs); F(mgp_sir_config, n);
+    F(mgp_sir_config, steps); F(mgp_sir_config, B); F(mgp_sir_config, partition_bytes); F(mgp_sir_config, epsilon);
+    F(mgp_sir_config, seed); F(mgp_sir_config, b_max); F(mgp_sir_config, use_graph);
+    F(mgp_sir_config, block_threads); F(mgp_sir_config, particles_per_thread); F(mgp_sir_config, reserved);
+    F(mgp_sir_config, reserved2);
+    S(mgp_sir_buffers); F(mgp_sir_buffers, x_dev); F(mgp_sir_buffers, w_dev); F(mgp_sir_buffers, xbar_dev);
+    F(mgp_sir_buffers, ancestors_dev); F(mgp_sir_buffers, ld); F(mgp_sir_buffers, device_bytes);
+    F(mgp_sir_buffers, accept_grid); F(mgp_sir_buffers, block_threads); F(mgp_sir_buffers, particles_per_thread);
     printf("\"end\": 0\n}\n");
     return 0;
 }

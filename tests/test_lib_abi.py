@@ -55,7 +55,8 @@ def test_struct_layouts_match_header(mgp, tmp_path):
                     os.path.join(ROOT, "tests", "helpers", "abi_layout.c")], check=True)
     layout = json.loads(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
     for name in ("mgp_params", "mgp_stats", "mgp_filter_desc", "mgp_batch_config", "mgp_batch_info",
-                 "mgp_server_config", "mgp_request", "mgp_request_result", "mgp_server_stats"):
+                 "mgp_server_config", "mgp_request", "mgp_request_result", "mgp_server_stats", "mgp_sir_config",
+                 "mgp_sir_buffers"):
         cls = getattr(mgp, name)
         assert ctypes.sizeof(cls) == layout[name], name
         for field, _ in cls._fields_:
