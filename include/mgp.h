@@ -310,9 +310,11 @@ int mgp_server_destroy(mgp_server* server);
  *            fused gather x_bar_t^(i) = x_t^(k_i);
  *   stage 3  the estimate x_hat_t = (sum_i x_bar_t^(i)) / n, in fp64.
  * Arithmetic of stage 1 is fp64; x and w are stored as fp32. The noise of
- * particle i, run r, step t is Box-Muller on words 0 and 1 of Philox4x32-10
- * at counter (t, 5, r, i), key = seed:
- *   u1 = (x0 + 1) 2^-32, u2 = x1 2^-32, v = sqrt(10) sqrt(-2 ln u1) cos(2 pi u2).
+ * particle i, run r, step t is sqrt(10) times Box-Muller in its two-output
+ * form on Philox4x32-10 at counter (t, 5, r, floor(i / 4)), key = seed:
+ * words (x0, x1) serve particles 4m, 4m+1 and (x2, x3) particles 4m+2, 4m+3;
+ * for a pair (a, b), u1 = (a + 1) 2^-32, u2 = b 2^-32, and the even particle
+ * takes sqrt(-2 ln u1) cos(2 pi u2), the odd one sqrt(-2 ln u1) sin(2 pi u2).
  * The resample of step t uses key seed + t * 2^32 and stream r. A run whose
  * weights all underflow to 0 at a step (status MGP_EWEIGHTS) keeps its
  * predicted particles for that step (x_bar_t = x_t) and its estimate is their

@@ -36,7 +36,7 @@
  *   tag 2  Megopolis o_b  index = 0,          block = b / 4, word b % 4
  *   tag 3  C1 partition   index = group g,    block = 0,     word 0
  *   tag 4  C2 partition   index = group g,    block = b / 4, word b % 4
- *   tag 5  SIR noise      index = particle i, block = step t, words 0, 1
+ *   tag 5  SIR noise      index = i / 4,      block = step t, Box-Muller pairs
  *
  * with group g = floor(i / 32) (the paper's warp index). Maps from 32-bit words:
  *   u in (0,1]   : m = 24 random bits, u = (m + 1) * 2^-24   (exact in fp32)
@@ -363,17 +363,23 @@ int mgp_oracle_gather(const float* states, int32_t n_states, int32_t d, const in
 #define OR_TAG_SIR_NOISE 5u
 #define OR_PI 3.14159265358979323846
 
-/* Standard normal draw of particle i at step t of run `run`: Box-Muller on
- * the first two words of Philox call (t, tag 5, run, i):
- *   u1 = (x0 + 1) 2^-32 in (0, 1],  u2 = x1 2^-32 in [0, 1),
- *   e  = sqrt(-2 ln u1) cos(2 pi u2)   (fp64). */
+/* Standard normal draw of particle i at step t of run `run`: Box-Muller in
+ * its two-output form. Philox call (t, tag 5, run, floor(i / 4)) gives words
+ * x0..x3; particles 4m and 4m+1 share the pair (x0, x1), particles 4m+2 and
+ * 4m+3 the pair (x2, x3). For a pair (a, b):
+ *   u1 = (a + 1) 2^-32 in (0, 1],  u2 = b 2^-32 in [0, 1),
+ *   e = sqrt(-2 ln u1) cos(2 pi u2) for even i, sqrt(-2 ln u1) sin(2 pi u2)
+ *   for odd i   (fp64). */
 double mgp_oracle_sir_normal(uint64_t seed, uint32_t run, uint32_t i, uint32_t t)
 {
     uint32_t x[4];
-    draw_words(seed, OR_TAG_SIR_NOISE, run, i, t, x);
-    double u1 = ((double)x[0] + 1.0) * 0x1p-32;
-    double u2 = (double)x[1] * 0x1p-32;
-    return sqrt(-2.0 * log(u1)) * cos(2.0 * OR_PI * u2);
+    draw_words(seed, OR_TAG_SIR_NOISE, run, i / 4u, t, x);
+    uint32_t pair = (i / 2u) % 2u;
+    double u1 = ((double)x[2u * pair] + 1.0) * 0x1p-32;
+    double u2 = (double)x[2u * pair + 1u] * 0x1p-32;
+    double radius = sqrt(-2.0 * log(u1));
+    double angle = 2.0 * OR_PI * u2;
+    return (i % 2u == 0u) ? radius * cos(angle) : radius * sin(angle);
 }
 
 /* Stage 1 of Algorithm 6 for n particles: predict from the resampled

@@ -9,16 +9,20 @@
 // normalisation because the Metropolis-family resamplers do not need it).
 //
 // One step of R runs (one filter per run, each n particles) is:
-//   stage 1  k_sir_predict_update  one thread per particle of every run;
-//                                  fp64 arithmetic, x and w stored as fp32;
+//   stage 1  k_sir_predict_update  one thread per four particles of every
+//                                  run; fp64 arithmetic, x and w stored as
+//                                  fp32;
 //   stage 2  the batched resampler (segmented reduction + mirror, finalize,
 //            accept loop with the fused gather x_bar_i = x_{k_i}), one filter
 //            per run;
 //   stage 3  k_sir_mean_partial + k_sir_mean_final: x_hat_t = sum(x_bar) / n
 //            in fp64, in a fixed order that depends on n only.
-// The noise v of particle i in run r at step t is Box-Muller on the first two
-// words of Philox4x32-10 at counter (t, 5, r, i) under the filter's seed; the
-// resample of step t runs under key seed + t * 2^32 with stream r.
+// The noise v of particle i in run r at step t is sqrt(10) times a standard
+// normal from Box-Muller in its two-output form: Philox4x32-10 at counter
+// (t, 5, r, floor(i / 4)) under the filter's seed gives two word pairs, pair
+// (i / 2) mod 2 serves particles 2 floor(i / 2) (cosine) and its odd
+// neighbour (sine). The resample of step t runs under key seed + t * 2^32
+// with stream r.
 //
 // A run whose weights all underflow to zero at some step (its resample
 // reports MGP_EWEIGHTS) keeps its predicted particles for that step: its
@@ -46,7 +50,24 @@ constexpr uint32_t kMeanChunk = 8192;  // particles per stage-3 partial sum
 constexpr uint32_t kRowAlign = 64;     // floats: every run's row starts 256-byte aligned
 constexpr double kPi = 3.14159265358979323846;
 
-// Stage 1 for particle i of run blockIdx.y.
+// Box-Muller in its two-output form for one pair of 32-bit words (a, b):
+// u1 = (a + 1) 2^-32 in (0, 1], u2 = b 2^-32 in [0, 1), radius
+// sqrt(-2 ln u1); the cosine output goes to the even particle of the pair,
+// the sine output to the odd one.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& even, double& odd)
+{
+    const double u1 = ((double)a + 1.0) * 0x1p-32;
+    const double u2 = (double)b * 0x1p-32;
+    const double radius = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(2.0 * kPi * u2, &sn, &cs);
+    even = radius * cs;
+    odd = radius * sn;
+}
+
+// Stage 1 for particles 4m .. 4m+3 of run blockIdx.y, m the thread's global
+// index: one Philox call (t, 5, r, m) gives two Box-Muller pairs, one normal
+// per particle.
 __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float* __restrict__ xbar, float* x,
                                                                     float* __restrict__ w,
                                                                     const double* __restrict__ z,
@@ -57,24 +78,50 @@ __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float*
                                                                     uint32_t key1)
 {
     const uint32_t r = blockIdx.y;
-    const uint32_t i = blockIdx.x * kSirThreads + threadIdx.x;
+    const uint32_t m = blockIdx.x * kSirThreads + threadIdx.x;
     // the resample of this step runs under key seed + t * 2^32
     if (blockIdx.x == 0 && threadIdx.x == 0) fd[r].key1 = key1 + t;
-    if (i >= n) return;
-    const uint64_t at = (uint64_t)r * ld + i;
+    const uint32_t i0 = 4u * m;
+    if (i0 >= n) return;
+    const uint64_t at = (uint64_t)r * ld + i0;  // rows are 256-byte aligned
+    const bool full = i0 + 4u <= n;
     // a run whose last resample failed continues from its predicted particles
-    const double xp = stats[r].status == MGP_OK ? (double)xbar[at] : (double)x[at];
-    const Words q = philox(t, kTagSirNoise, r, i, key0, key1);
-    const double u1 = ((double)q.x0 + 1.0) * 0x1p-32;  // (0, 1]
-    const double u2 = (double)q.x1 * 0x1p-32;          // [0, 1)
-    const double e = sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
-    const double v = sigma_v * e;
-    const double xn = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + drift + v;
-    const float xf = (float)xn;
-    const double xd = (double)xf;
-    const double res = z[(uint64_t)r * zld + t] - xd * xd / 20.0;
-    x[at] = xf;
-    w[at] = (float)exp(-0.5 * res * res);
+    const float* src = stats[r].status == MGP_OK ? xbar : x;
+    float xin[4];
+    if (full) {
+        const float4 v = *reinterpret_cast<const float4*>(src + at);
+        xin[0] = v.x;
+        xin[1] = v.y;
+        xin[2] = v.z;
+        xin[3] = v.w;
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) xin[k] = i0 + k < n ? src[at + k] : 0.0f;
+    }
+    const Words q = philox(t, kTagSirNoise, r, m, key0, key1);
+    double e[4];
+    box_muller(q.x0, q.x1, e[0], e[1]);
+    box_muller(q.x2, q.x3, e[2], e[3]);
+    const double zt = z[(uint64_t)r * zld + t];
+    float xo[4], wo[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const double xp = (double)xin[k];
+        const double xn = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + drift + sigma_v * e[k];
+        xo[k] = (float)xn;
+        const double xd = (double)xo[k];
+        const double res = zt - xd * xd / 20.0;
+        wo[k] = (float)exp(-0.5 * res * res);
+    }
+    if (full) {
+        *reinterpret_cast<float4*>(x + at) = make_float4(xo[0], xo[1], xo[2], xo[3]);
+        *reinterpret_cast<float4*>(w + at) = make_float4(wo[0], wo[1], wo[2], wo[3]);
+    } else {
+        for (uint32_t k = 0; k < 4 && i0 + k < n; ++k) {
+            x[at + k] = xo[k];
+            w[at + k] = wo[k];
+        }
+    }
 }
 
 // Stage 3, first pass: the fp64 sum of particles [c * kMeanChunk, ...) of run
@@ -236,7 +283,8 @@ void advance(mgp_sir_filter* f)
 int enqueue_predict(mgp_sir_filter* f, uint32_t t, hipStream_t s)
 {
     const double drift = 8.0 * cos(1.2 * (double)t);
-    const dim3 grid((f->n + kSirThreads - 1) / kSirThreads, f->R);
+    const uint32_t quads = (f->n + 3u) / 4u;
+    const dim3 grid((quads + kSirThreads - 1) / kSirThreads, f->R);
     hipLaunchKernelGGL(k_sir_predict_update, grid, dim3(kSirThreads), 0, s, f->xbar, f->x, f->w, f->z, f->d_stats,
                        f->d_fd, f->ld, f->zld, f->n, t, drift, f->sigma_v, f->key0, f->key1);
     return check_launch("SIR predict/update");

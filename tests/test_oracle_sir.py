@@ -29,6 +29,13 @@ def test_noise_is_standard_normal():
     e3 = np.array([oracle.sir_normal(11, 4, i, 5) for i in range(20000)])
     assert abs(np.corrcoef(e, e2)[0, 1]) < 5 / math.sqrt(e.size)
     assert abs(np.corrcoef(e, e3)[0, 1]) < 5 / math.sqrt(e.size)
+    # Box-Muller pairs (particles 2m, 2m+1): uncorrelated, and the squared
+    # radius e_2m^2 + e_2m+1^2 is chi-square with 2 degrees of freedom
+    a, b = e[0::2], e[1::2]
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / math.sqrt(a.size)
+    assert stats.kstest(a * a + b * b, "expon", args=(0, 2)).pvalue > 1e-3
+    # the two pairs of one generator call are independent of each other
+    assert abs(np.corrcoef(e[0::4], e[2::4])[0, 1]) < 5 / math.sqrt(e.size / 4)
 
 
 @pytest.mark.parametrize("c,t", [(-3.0, 1), (0.5, 2), (2.0, 7), (10.0, 40), (0.0, 13)])
