@@ -195,7 +195,8 @@ def batched_section(torch, mgp, inputs, runs):
 def sweep_section(torch, mgp, inputs):
     """The paper's timing experiment on this GPU: resample time (reduction, B,
     accept loop; no gather) at N = 2^22 for Megopolis, Metropolis, C1 and C2
-    at 128 and 2048 bytes, y = 0..4, eps = 0.01; median of 5 runs."""
+    at 128 and 2048 bytes, y = 0..4, eps = 0.01; median of 5 runs. Then the
+    partition-size study: C1 and C2 at 128..2048 bytes at y = 4."""
     import numpy as np
     dev = torch.device("cuda:0")
     n = 1 << 22
@@ -218,8 +219,24 @@ def sweep_section(torch, mgp, inputs):
                 if k:
                     times.append(a.elapsed_time(b))
             out.setdefault(key, {})[f"y{y}"] = {"ms": float(np.median(times)), "B": r.last_stats()["B"]}
+    # the partition-size study: C1 and C2 at every partition size, y = 4
+    w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
+    parts = {}
+    for v in ("c1", "c2"):
+        for ps in (128, 256, 512, 1024, 2048):
+            times = []
+            for k in range(6):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                r.resample(w, v, epsilon=0.01, seed=k, partition_bytes=ps, out=anc)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if k:
+                    times.append(a.elapsed_time(b))
+            parts[f"{v}-ps{ps}"] = float(np.median(times))
     return {"workload": "N=2^22, Gaussian-likelihood weights, eps=0.01; resample = reduction + B + accept loop "
-                        "(no gather); median of 5 runs", "ms": out}
+                        "(no gather); median of 5 runs", "ms": out,
+            "partition_sizes_y4_ms": parts}
 
 
 def table2():

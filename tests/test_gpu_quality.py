@@ -28,7 +28,7 @@ def env():
     return torch, torch.device("cuda:0"), mgp
 
 
-@pytest.mark.parametrize("variant,ps,y,expect", CASES, ids=[f"{v}-y{y}" for v, ps, y, _ in CASES])
+@pytest.mark.parametrize("variant,ps,y,expect", CASES, ids=[f"{v}-ps{ps}-y{y}" for v, ps, y, _ in CASES])
 def test_mse_over_n_at_2pow20(env, variant, ps, y, expect):
     torch, dev, mgp = env
     n = GOLDEN["n"]

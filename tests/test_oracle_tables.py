@@ -1,6 +1,7 @@
 """Statistical pin of the whole oracle against the paper's own measurements:
-MSE/N at N = 32768 for Megopolis, Metropolis, C1 and C2 (Tables 3-6, first
-row), Gaussian-likelihood weights, eps = 0.01, B from eq. (proposition).
+MSE/N at N = 32768 for Megopolis, Metropolis, and C1 and C2 at partition
+sizes 128-2048 bytes (Tables 3-6, first row), Gaussian-likelihood weights,
+eps = 0.01, B from eq. (proposition).
 
 The paper averages 16 weight sequences x 256 runs; this test uses 4
 sequences and fewer runs, and allows 4 standard errors of its own estimate
@@ -17,8 +18,11 @@ from paper_2109_13504_amd import inputs
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mse_over_n_N32768.json")))
 RUNS_PER_SEQ = {0: 6, 1: 6, 2: 4, 3: 2, 4: 1}
+# partition sizes 256-1024 are checked here at y <= 2 only (the costly
+# y = 3, 4 chains of every partition size run on the GPU at N = 2^20)
 CASES = [(row["variant"], row["partition_bytes"], y, row["mse_over_n"][y])
-         for row in GOLDEN["rows"] for y in range(5)]
+         for row in GOLDEN["rows"] for y in range(5)
+         if row["partition_bytes"] in (128, 2048) or y <= 2]
 
 
 @pytest.mark.parametrize("variant,ps,y,expect", CASES,
