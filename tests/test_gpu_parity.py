@@ -153,7 +153,7 @@ def test_megopolis_uniform_weights_permutation_at_scale(torch_dev, mgp):
     assert torch.equal(torch.sort(anc.long()).values, torch.arange(n, device=dev))
 
 
-@pytest.mark.parametrize("d", [1, 3, 4, 8, 16])
+@pytest.mark.parametrize("d", [1, 3, 4, 8, 12, 16, 32])
 def test_gather_shapes(torch_dev, mgp, d):
     torch, dev = torch_dev
     n_states, n_out = 5000, 7777
