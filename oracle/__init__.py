@@ -67,6 +67,9 @@ def lib():
         L.mgp_oracle_resample.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.c_uint32, _u32p, _i32p, _u64p]
         L.mgp_oracle_resample.restype = ctypes.c_int
+        L.mgp_oracle_resample_m.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
+                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u32p, _i32p]
+        L.mgp_oracle_resample_m.restype = ctypes.c_int
         L.mgp_oracle_resample_subset.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
                                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u32p,
                                                  _i32p, ctypes.c_int32, _i32p]
@@ -178,6 +181,19 @@ def resample(w: np.ndarray, variant, B: int, seed: int, stream_id: int = 0, part
         raise OracleError(rc, "mgp_oracle_resample")
     if return_accepts:
         return anc, int(acc.value)
+    return anc
+
+
+def resample_m(w: np.ndarray, m: int, variant, B: int, seed: int, stream_id: int = 0,
+               partition_bytes: int = 128) -> np.ndarray:
+    """M != N: m ancestors from the n = len(w) weighted inputs."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    anc = np.empty(m, dtype=np.int32)
+    scratch = np.zeros(max(B, 1), dtype=np.uint32)
+    rc = lib().mgp_oracle_resample_m(_ptr(w, _f32p), w.size, m, _variant(variant), B, seed, stream_id,
+                                     partition_bytes, _ptr(scratch, _u32p), _ptr(anc, _i32p))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_resample_m")
     return anc
 
 

@@ -19,6 +19,7 @@
  *   - number of iterations B         : eq. (bcalc) in Section 3 and
  *                                      eq. (proposition), Section 4.1
  *   - particle copy x_bar_i = x_k    : last statement of Algorithms 2-5
+ *   - M != N resampling              : the closing discussion (Section 8)
  *   - SIR application (predict, update, estimate): Algorithm 6, Section 7
  *
  * The paper fixes the algorithms but not the random-number generator (it used
@@ -174,9 +175,12 @@ static uint32_t partition_index(uint32_t n, uint32_t n_w, uint32_t part_word, ui
 }
 
 /* Candidate index j for particle i at iteration b, for each variant.
- * `offsets` holds o_0..o_{B-1} (Megopolis only). */
+ * `offsets` holds o_0..o_{B-1} (Megopolis only). `pos` is the input position
+ * the particle's chain started from (i itself when inputs and outputs are
+ * the same particles; i mod N when M != N): the Megopolis segment arithmetic
+ * uses it, while the random draws and the C1/C2 group use i. */
 static uint32_t proposal(int variant, uint32_t n, uint32_t n_w, uint64_t seed, uint32_t stream_id,
-                         const uint32_t* offsets, uint32_t i, uint32_t b)
+                         const uint32_t* offsets, uint32_t i, uint32_t pos, uint32_t b)
 {
     uint32_t x[4], px[4];
     switch (variant) {
@@ -192,7 +196,7 @@ static uint32_t proposal(int variant, uint32_t n, uint32_t n_w, uint64_t seed, u
         draw_words(seed, OR_TAG_J, stream_id, i, b / 4u, x);
         return partition_index(n, n_w, px[b % 4u], x[b % 4u]);
     default: /* OR_MEGOPOLIS */
-        return mgp_oracle_megopolis_index(i, offsets[b], n);
+        return mgp_oracle_megopolis_index(pos, offsets[b], n);
     }
 }
 
@@ -206,16 +210,16 @@ static int check_common(int variant, int32_t n, uint32_t partition_bytes)
     return OR_OK;
 }
 
-/* One particle's chain: k <- i, then B accept/reject steps against candidate
+/* One particle's chain: k <- pos (= i for M = N), then B accept/reject steps against candidate
  * j with the ratio test u <= w_j / w_k written as the fp32 product
  * u * w_k <= w_j (ties accept). Returns the ancestor k. */
 static int32_t run_chain(const float* w, uint32_t n, int variant, uint32_t B, uint64_t seed,
                          uint32_t stream_id, uint32_t n_w, const uint32_t* offsets, uint32_t i,
-                         uint64_t* accepts)
+                         uint32_t pos, uint64_t* accepts)
 {
-    uint32_t k = i;
+    uint32_t k = pos;
     for (uint32_t b = 0; b < B; ++b) {
-        uint32_t j = proposal(variant, n, n_w, seed, stream_id, offsets, i, b);
+        uint32_t j = proposal(variant, n, n_w, seed, stream_id, offsets, i, pos, b);
         float u = mgp_oracle_draw_u(seed, stream_id, i, b);
         float p = u * w[k];
         if (p <= w[j]) {
@@ -243,7 +247,32 @@ int mgp_oracle_resample(const float* w, int32_t n, int variant, uint32_t B, uint
     uint32_t n_w = partition_bytes / 4u;
     for (uint32_t i = 0; i < (uint32_t)n; ++i)
         ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w,
-                                 offsets_scratch, i, accepts);
+                                 offsets_scratch, i, i, accepts);
+    return OR_OK;
+}
+
+/* M != N resampling (the paper's closing discussion: for D-PMC-style use the
+ * Megopolis offsets range over the number of inputs): m ancestors from n
+ * weighted inputs. Output i in [0, m) starts its chain at input i mod n;
+ * offsets o_b ~ U{0, n-1} and candidates are taken over the n inputs, with
+ * the Megopolis segment arithmetic on the start position; the u and j draws
+ * and the C1/C2 group floor(i / 32) are those of output i. With m == n this
+ * is mgp_oracle_resample. */
+int mgp_oracle_resample_m(const float* w, int32_t n, int32_t m, int variant, uint32_t B, uint64_t seed,
+                          uint32_t stream_id, uint32_t partition_bytes, uint32_t* offsets_scratch,
+                          int32_t* ancestors)
+{
+    int rc = check_common(variant, n, partition_bytes);
+    if (rc) return rc;
+    if (m < 1) return OR_EINVAL;
+    if (variant == OR_MEGOPOLIS) {
+        if (!offsets_scratch) return OR_EINVAL;
+        mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
+    }
+    uint32_t n_w = partition_bytes / 4u;
+    for (uint32_t i = 0; i < (uint32_t)m; ++i)
+        ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, offsets_scratch, i,
+                                 i % (uint32_t)n, NULL);
     return OR_OK;
 }
 
@@ -263,7 +292,7 @@ int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t 
     for (int32_t c = 0; c < count; ++c) {
         if (idx[c] < 0 || idx[c] >= n) return OR_EINVAL;
         ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w,
-                                 offsets_scratch, (uint32_t)idx[c], NULL);
+                                 offsets_scratch, (uint32_t)idx[c], (uint32_t)idx[c], NULL);
     }
     return OR_OK;
 }
@@ -284,7 +313,7 @@ int mgp_oracle_trace(int32_t n, int variant, uint32_t B, uint64_t seed, uint32_t
     uint32_t n_w = partition_bytes / 4u;
     for (uint32_t b = 0; b < B; ++b) {
         j_out[b] = proposal(variant, (uint32_t)n, n_w, seed, stream_id, offsets_scratch,
-                            (uint32_t)i, b);
+                            (uint32_t)i, (uint32_t)i, b);
         u_out[b] = mgp_oracle_draw_u(seed, stream_id, (uint32_t)i, b);
     }
     return OR_OK;
