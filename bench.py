@@ -326,6 +326,38 @@ def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20,
             "runs": R, "n": n, "steps": T, "rows": out}
 
 
+def m_neq_n_section(torch, mgp, inputs):
+    """M != N resampling (Section 8's D-PMC remark): Megopolis, B from
+    eps = 0.01 on Gaussian-likelihood weights with y = 4, N inputs -> M
+    outputs for (2^24 -> 2^22) and (2^22 -> 2^24); whole mgp_resample_m call
+    (reduction, B, offsets, accept loop), median of 5."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for ln, lm in ((24, 22), (22, 24)):
+        n, m = 1 << ln, 1 << lm
+        w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
+        anc = torch.empty(m, dtype=torch.int32, device=dev)
+        r = mgp.Resampler(n)
+        times = []
+        for k in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            r.resample_m(w, m, "megopolis", epsilon=0.01, seed=k, out=anc)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if k:
+                times.append(a.elapsed_time(b))
+        B = r.last_stats()["B"]
+        ms = float(np.median(times))
+        out[f"n2^{ln}_m2^{lm}"] = {"ms": ms, "B": B, "outputs_per_s": m / (ms * 1e-3),
+                                   "kernel": "mirrored" if m <= n else "generic",
+                                   "effective_GBs": 4.0 * m * (B + 2) / (ms * 1e-3) / 1e9}
+        del w, anc, r
+    return {"workload": "Megopolis, Gaussian-likelihood weights y=4, eps=0.01; N inputs -> M outputs", "runs": out}
+
+
 def serving_section(torch, mgp, inputs, n_requests, streams=4, max_batch=8, max_particles=1 << 22):
     """Poisson stream of requests, N = round(2^U(12, 22)), y ~ U[0, 4], D = 16
     states resident on the device, Megopolis, admitted by HBM budget. The
@@ -506,6 +538,9 @@ def main():
     if not args.no_sweep:
         log("[bench] per-variant sweep at N=2^22")
         result["paper_sweep"] = sweep_section(torch, mgp, inputs)
+        log("[bench] M != N")
+        result["m_neq_n"] = m_neq_n_section(torch, mgp, inputs)
+        log(f"[bench] M != N: {result['m_neq_n']['runs']}")
 
     if not args.no_serving:
         log("[bench] serving")

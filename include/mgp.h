@@ -98,6 +98,19 @@ int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes);
 int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
                  mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
 
+/* RESAMPLE with M != N: m ancestors drawn from n weighted inputs, as the
+ * paper's closing discussion (Section 8) proposes for D-PMC-style samplers,
+ * with the Megopolis offsets ranging over the input count. Output i in
+ * [0, m) starts its chain at input i mod n and runs the B steps of
+ * mgp_resample with its own random draws (Philox counter index i; C1/C2
+ * group floor(i / 32)); candidates and offsets range over [0, n). With
+ * m == n the result equals mgp_resample's.
+ * w_dev: n fp32 weights; ancestors_dev: m int32, each in [0, n); workspace:
+ * mgp_workspace_size(n, params) bytes; stats_dev, stream: as mgp_resample.
+ * Megopolis with m <= n runs the mirrored kernel; m > n the generic one. */
+int mgp_resample_m(const float* w_dev, int32_t n, int32_t m, const mgp_params* params, int32_t* ancestors_dev,
+                   mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+
 /* Steps 1 and 2 of mgp_resample only: the reduction, B, and (for
  * MGP_MEGOPOLIS) the offsets, kept in the workspace for a following
  * mgp_resample_prepared. The paper leaves B to be pre-estimated when its

@@ -175,15 +175,18 @@ struct Unroll {
     static constexpr uint32_t value = (V == kMegopolis) ? 5u : 20u;
 };
 
-// The B-step chain of particle i; returns its ancestor.
+// The B-step chain of particle i; returns its ancestor. The chain starts at
+// input position pos (i itself when inputs and outputs are the same
+// particles, i mod n for M != N resampling): the Megopolis segment
+// arithmetic uses pos, the random draws and the C1/C2 group use i.
 template <int V, bool Narrow>
-__device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
+__device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, uint32_t pos)
 {
     const float* __restrict__ w = P.w;
-    uint32_t k = i;
-    float wk = load_weight<Narrow>(w, i);
-    const uint32_t i_aligned = i & ~(kSegment - 1u);
-    const uint32_t i_low = i & (kSegment - 1u);
+    uint32_t k = pos;
+    float wk = load_weight<Narrow>(w, pos);
+    const uint32_t i_aligned = pos & ~(kSegment - 1u);
+    const uint32_t i_low = pos & (kSegment - 1u);
     const uint32_t group = i / kSegment;
 
     uint32_t c1_part = 0;
@@ -270,6 +273,12 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
         }
     }
     return k;
+}
+
+template <int V, bool Narrow>
+__device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
+{
+    return run_chain<V, Narrow>(P, i, i);
 }
 
 // ---------------------------------------------------------------------------

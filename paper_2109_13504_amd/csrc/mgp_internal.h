@@ -79,6 +79,9 @@ uint32_t reduce_chunk(uint32_t n, uint32_t blocks);
 int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,
                             mgp_stats* st_user, hipStream_t stream);
 int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream);
+// The accept loop for m outputs drawn from n weighted inputs (M != N).
+int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char* ws, int32_t* anc,
+                   hipStream_t stream);
 int enqueue_gather(const float* states, uint32_t n_states, uint32_t d, const int32_t* anc, uint32_t n_out,
                    float* out, hipStream_t stream);
 

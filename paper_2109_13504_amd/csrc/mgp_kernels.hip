@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_finalize(const Partial* __re
 // 3. The accept loop, one particle per thread.
 // ---------------------------------------------------------------------------
 template <int V, bool Narrow>
-__global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restrict__ w, uint32_t n,
+__global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restrict__ w, uint32_t n, uint32_t m,
                                                            const mgp_stats* __restrict__ st,
                                                            const uint32_t* __restrict__ offsets, uint32_t key0,
                                                            uint32_t key1, uint32_t stream_id, uint32_t n_w,
@@ -94,19 +94,21 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
     // the stats must come from the reduction of this very call (same n,
     // variant, seed and stream), and B must fit the workspace
     const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
-    if (i >= n) return;
+    if (i >= m) return;
     if (!ok) {
         anc[i] = -1;
         return;
     }
     LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part};
-    anc[i] = (int32_t)run_chain<V, Narrow>(P, i);
+    // output i starts at input i mod n (i itself when m <= n)
+    const uint32_t pos = i < n ? i : i % n;
+    anc[i] = (int32_t)run_chain<V, Narrow>(P, i, pos);
 }
 
 // Megopolis over the mirrored weights, kMegopolisPPT particles per thread.
 template <int P>
 __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* __restrict__ mirror, uint32_t n,
-                                                                   const mgp_stats* __restrict__ st,
+                                                                   uint32_t m, const mgp_stats* __restrict__ st,
                                                                    const uint32_t* __restrict__ offsets,
                                                                    uint32_t key0, uint32_t key1, uint32_t stream_id,
                                                                    uint32_t tag, uint32_t b_cap,
@@ -118,16 +120,16 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* 
     if (!ok) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
-            if (i0 + kLoopThreads * p < n) anc[i0 + kLoopThreads * p] = -1;
+            if (i0 + kLoopThreads * p < m) anc[i0 + kLoopThreads * p] = -1;
         return;
     }
-    // every lane runs, also past n: the mirror's padding keeps those loads in
-    // bounds, and only real particles store
+    // every lane runs, also past m (m <= n here): the mirror's padding keeps
+    // those loads in bounds, and only real outputs store
     uint32_t k[P];
     megopolis_mirror_chain<P>(reinterpret_cast<const char*>(mirror), offsets, n, B, key0, key1, stream_id, i0, k);
 #pragma unroll
     for (int p = 0; p < P; ++p)
-        if (i0 + kLoopThreads * p < n) anc[i0 + kLoopThreads * p] = (int32_t)k[p];
+        if (i0 + kLoopThreads * p < m) anc[i0 + kLoopThreads * p] = (int32_t)k[p];
 }
 
 // ---------------------------------------------------------------------------
@@ -264,49 +266,55 @@ int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool ma
 }
 
 template <int V>
-static void launch_loop(bool narrow, dim3 grid, hipStream_t s, const float* w, uint32_t n, const mgp_stats* st,
-                        const uint32_t* offs, uint32_t k0, uint32_t k1, uint32_t sid, uint32_t n_w,
-                        uint32_t n_part, uint32_t tag, uint32_t b_cap, int32_t* anc)
+static void launch_loop(bool narrow, dim3 grid, hipStream_t s, const float* w, uint32_t n, uint32_t m,
+                        const mgp_stats* st, const uint32_t* offs, uint32_t k0, uint32_t k1, uint32_t sid,
+                        uint32_t n_w, uint32_t n_part, uint32_t tag, uint32_t b_cap, int32_t* anc)
 {
     if (narrow)
-        hipLaunchKernelGGL((k_resample<V, true>), grid, dim3(kLoopThreads), 0, s, w, n, st, offs, k0, k1, sid, n_w,
-                           n_part, tag, b_cap, anc);
+        hipLaunchKernelGGL((k_resample<V, true>), grid, dim3(kLoopThreads), 0, s, w, n, m, st, offs, k0, k1, sid,
+                           n_w, n_part, tag, b_cap, anc);
     else
-        hipLaunchKernelGGL((k_resample<V, false>), grid, dim3(kLoopThreads), 0, s, w, n, st, offs, k0, k1, sid, n_w,
-                           n_part, tag, b_cap, anc);
+        hipLaunchKernelGGL((k_resample<V, false>), grid, dim3(kLoopThreads), 0, s, w, n, m, st, offs, k0, k1, sid,
+                           n_w, n_part, tag, b_cap, anc);
 }
 
 int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream)
+{
+    return enqueue_loop_m(w, n, n, p, ws, anc, stream);
+}
+
+int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char* ws, int32_t* anc,
+                   hipStream_t stream)
 {
     const mgp_stats* st = reinterpret_cast<const mgp_stats*>(ws + kWsStatsOffset);
     const uint32_t* offs = reinterpret_cast<const uint32_t*>(ws + kWsOffsetsOffset);
     const uint32_t n_w = p.partition_bytes / 4u;
     const uint32_t n_part = (uint32_t)(((uint64_t)n + n_w - 1u) / n_w);
     const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
-    const dim3 grid((n + kLoopThreads - 1u) / kLoopThreads);
+    const dim3 grid((m + kLoopThreads - 1u) / kLoopThreads);
     const bool narrow = n <= (1u << 30);
     const uint32_t tag = call_tag(n, p.variant, p.seed, p.stream_id);
     const uint32_t cap = p.b_max;
-    if (uses_mirror(n, p.variant)) {
+    if (uses_mirror(n, p.variant) && m <= n) {
         constexpr int P = kMegopolisPPT;
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
-        const dim3 g((n + kLoopThreads * P - 1u) / (kLoopThreads * P));
-        hipLaunchKernelGGL((k_megopolis_mirror<P>), g, dim3(kLoopThreads), 0, stream, mirror, n, st, offs, k0, k1,
+        const dim3 g((m + kLoopThreads * P - 1u) / (kLoopThreads * P));
+        hipLaunchKernelGGL((k_megopolis_mirror<P>), g, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs, k0, k1,
                            p.stream_id, tag, cap, anc);
         return check_launch("megopolis kernel");
     }
     switch (p.variant) {
     case kMetropolis:
-        launch_loop<kMetropolis>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kMetropolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
         break;
     case kC1:
-        launch_loop<kC1>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kC1>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
         break;
     case kC2:
-        launch_loop<kC2>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kC2>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
         break;
     default:
-        launch_loop<kMegopolis>(narrow, grid, stream, w, n, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kMegopolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
         break;
     }
     return check_launch("resample kernel");
@@ -418,6 +426,25 @@ int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_
     rc = enqueue_reduce_finalize(w_dev, (uint32_t)n, p, p.variant == kMegopolis, ws, stats_dev, s);
     if (rc) return rc;
     return enqueue_loop(w_dev, (uint32_t)n, p, ws, ancestors_dev, s);
+}
+
+int mgp_resample_m(const float* w_dev, int32_t n, int32_t m, const mgp_params* params, int32_t* ancestors_dev,
+                   mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes_, void* stream)
+{
+    clear_error();
+    if (!w_dev || !ancestors_dev) return fail(MGP_EINVAL, "w_dev and ancestors_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    if (m < 1) return fail(MGP_EINVAL, "m must be >= 1 (got %d)", m);
+    Params p;
+    int rc = normalize_params(params, &p);
+    if (rc) return rc;
+    rc = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
+    if (rc) return rc;
+    char* ws = static_cast<char*>(workspace_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = enqueue_reduce_finalize(w_dev, (uint32_t)n, p, p.variant == kMegopolis, ws, stats_dev, s);
+    if (rc) return rc;
+    return enqueue_loop_m(w_dev, (uint32_t)n, (uint32_t)m, p, ws, ancestors_dev, s);
 }
 
 int mgp_gather(const float* states_dev, int32_t n_states, int32_t d, const int32_t* ancestors_dev, int32_t n_out,

@@ -130,6 +130,7 @@ def lib():
         L.mgp_workspace_size.argtypes = [ctypes.c_int32, P, ctypes.POINTER(ctypes.c_size_t)]
         L.mgp_resample.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_compute_B.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
+        L.mgp_resample_m.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, P, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_resample_prepared.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_gather.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
         L.mgp_batch_plan_create.argtypes = [ctypes.POINTER(mgp_filter_desc), ctypes.c_int32,
@@ -172,7 +173,7 @@ def lib():
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
         L.mgp_version.argtypes = []
-        for f in ("mgp_workspace_size", "mgp_resample", "mgp_compute_B", "mgp_resample_prepared", "mgp_gather",
+        for f in ("mgp_workspace_size", "mgp_resample", "mgp_resample_m", "mgp_compute_B", "mgp_resample_prepared", "mgp_gather",
                   "mgp_version"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -214,6 +215,12 @@ def mgp_resample(w_dev: int, n: int, params: mgp_params, ancestors_dev: int, sta
                  workspace_bytes: int, stream: int) -> None:
     _check(lib().mgp_resample(w_dev, n, ctypes.byref(params), ancestors_dev, stats_dev or None, workspace_dev,
                               workspace_bytes, stream or None), "mgp_resample")
+
+
+def mgp_resample_m(w_dev: int, n: int, m: int, params: mgp_params, ancestors_dev: int, stats_dev: int,
+                   workspace_dev: int, workspace_bytes: int, stream: int) -> None:
+    _check(lib().mgp_resample_m(w_dev, n, m, ctypes.byref(params), ancestors_dev, stats_dev or None, workspace_dev,
+                                workspace_bytes, stream or None), "mgp_resample_m")
 
 
 def mgp_compute_B(w_dev: int, n: int, params: mgp_params, stats_dev: int, workspace_dev: int,
@@ -417,6 +424,18 @@ class Resampler:
         p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
         mgp_resample(w.data_ptr(), n, p, out.data_ptr(), self.stats.data_ptr(), self.workspace.data_ptr(),
                      self.ws_bytes, current_stream() if stream is None else stream)
+        return out
+
+    def resample_m(self, w, m: int, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
+                   stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+        """m ancestors from the n = w.numel() weighted inputs (M != N)."""
+        _require_weights(w)
+        torch = _torch()
+        if out is None:
+            out = torch.empty(int(m), dtype=torch.int32, device=w.device)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        mgp_resample_m(w.data_ptr(), w.numel(), int(m), p, out.data_ptr(), self.stats.data_ptr(),
+                       self.workspace.data_ptr(), self.ws_bytes, current_stream() if stream is None else stream)
         return out
 
     def compute_B(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
