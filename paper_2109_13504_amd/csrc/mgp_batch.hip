@@ -403,9 +403,12 @@ int enqueue_batch(int variant, const LoopShape& sh, const FilterDev* d_fd, uint3
                   uint32_t n_rt, Partial* d_parts, mgp_stats* d_stats, const LTile* d_lt, uint32_t grid,
                   const uint32_t* d_qoff, uint32_t* d_qcount, uint32_t nxcd, uint32_t d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_reduce, dim3(n_rt), dim3(kReduceThreads), 0, s, d_fd, d_rt, d_parts);
-    int rc = check_launch("batch reduce");
-    if (rc) return rc;
+    int rc;
+    if (n_rt > 0) {
+        hipLaunchKernelGGL(k_batch_reduce, dim3(n_rt), dim3(kReduceThreads), 0, s, d_fd, d_rt, d_parts);
+        rc = check_launch("batch reduce");
+        if (rc) return rc;
+    }
     hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(kReduceThreads), 0, s, d_fd, d_parts, d_stats, d_qcount,
                        (uint32_t)kMaxXcd);
     rc = check_launch("batch finalize");

@@ -62,7 +62,9 @@ void build_tile_table(const std::vector<uint32_t>& n, const std::vector<double>&
                       std::vector<LTile>& table, uint32_t* qoff);
 
 // Enqueues one batched run: the segmented reduction, one finalize block per
-// filter, and the accept loop with the fused gather.
+// filter, and the accept loop with the fused gather. With n_rt == 0 the
+// reduction is skipped: the producer of the weights has already written
+// every filter's partials (and, for Megopolis, its mirror).
 int enqueue_batch(int variant, const LoopShape& sh, const FilterDev* d_fd, uint32_t count, const RTile* d_rt,
                   uint32_t n_rt, Partial* d_parts, mgp_stats* d_stats, const LTile* d_lt, uint32_t grid,
                   const uint32_t* d_qoff, uint32_t* d_qcount, uint32_t nxcd, uint32_t d, hipStream_t s);

@@ -11,10 +11,13 @@
 // One step of R runs (one filter per run, each n particles) is:
 //   stage 1  k_sir_predict_update  one thread per four particles of every
 //                                  run; fp64 arithmetic, x and w stored as
-//                                  fp32;
-//   stage 2  the batched resampler (segmented reduction + mirror, finalize,
-//            accept loop with the fused gather x_bar_i = x_{k_i}), one filter
-//            per run;
+//                                  fp32; it also writes the resampler's
+//                                  per-block partials and the Megopolis
+//                                  mirror (the reduction the batched
+//                                  resampler would otherwise run);
+//   stage 2  the batched resampler from its finalize step on (B, offsets,
+//            validation), then the accept loop with the fused gather
+//            x_bar_i = x_{k_i}, one filter per run;
 //   stage 3  k_sir_mean_partial + k_sir_mean_final: x_hat_t = sum(x_bar) / n
 //            in fp64, in a fixed order that depends on n only.
 // The noise v of particle i in run r at step t is sqrt(10) times a standard
@@ -67,61 +70,97 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& even,
 
 // Stage 1 for particles 4m .. 4m+3 of run blockIdx.y, m the thread's global
 // index: one Philox call (t, 5, r, m) gives two Box-Muller pairs, one normal
-// per particle.
+// per particle. The kernel is bound by fp64 VALU issue, so it also does the
+// resampler's per-weight work while the weights are in registers: the
+// block's partial (fp32 max, fp64 sum, validity) for the finalize step, and
+// for Megopolis the mirror M[i] = M[i + n] = w_i (plus M[2n + k] = w_{k mod n}
+// for k < kMirrorPad).
 __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float* __restrict__ xbar, float* x,
                                                                     float* __restrict__ w,
                                                                     const double* __restrict__ z,
                                                                     const mgp_stats* __restrict__ stats,
-                                                                    FilterDev* __restrict__ fd, uint64_t ld,
+                                                                    FilterDev* __restrict__ fd,
+                                                                    Partial* __restrict__ parts, uint64_t ld,
                                                                     uint32_t zld, uint32_t n, uint32_t t,
                                                                     double drift, double sigma_v, uint32_t key0,
                                                                     uint32_t key1)
 {
     const uint32_t r = blockIdx.y;
     const uint32_t m = blockIdx.x * kSirThreads + threadIdx.x;
+    float* mirror = fd[r].mirror;
+    const uint32_t part_base = fd[r].part_base;
     // the resample of this step runs under key seed + t * 2^32
     if (blockIdx.x == 0 && threadIdx.x == 0) fd[r].key1 = key1 + t;
     const uint32_t i0 = 4u * m;
-    if (i0 >= n) return;
-    const uint64_t at = (uint64_t)r * ld + i0;  // rows are 256-byte aligned
-    const bool full = i0 + 4u <= n;
-    // a run whose last resample failed continues from its predicted particles
-    const float* src = stats[r].status == MGP_OK ? xbar : x;
-    float xin[4];
-    if (full) {
-        const float4 v = *reinterpret_cast<const float4*>(src + at);
-        xin[0] = v.x;
-        xin[1] = v.y;
-        xin[2] = v.z;
-        xin[3] = v.w;
-    } else {
+    float mx = 0.0f;
+    double s = 0.0;
+    uint32_t bad = 0;
+    if (i0 < n) {
+        const uint64_t at = (uint64_t)r * ld + i0;  // rows are 256-byte aligned
+        const bool full = i0 + 4u <= n;
+        // a run whose last resample failed continues from its predicted particles
+        const float* src = stats[r].status == MGP_OK ? xbar : x;
+        float xin[4];
+        if (full) {
+            const float4 v = *reinterpret_cast<const float4*>(src + at);
+            xin[0] = v.x;
+            xin[1] = v.y;
+            xin[2] = v.z;
+            xin[3] = v.w;
+        } else {
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k) xin[k] = i0 + k < n ? src[at + k] : 0.0f;
-    }
-    const Words q = philox(t, kTagSirNoise, r, m, key0, key1);
-    double e[4];
-    box_muller(q.x0, q.x1, e[0], e[1]);
-    box_muller(q.x2, q.x3, e[2], e[3]);
-    const double zt = z[(uint64_t)r * zld + t];
-    float xo[4], wo[4];
+            for (uint32_t k = 0; k < 4; ++k) xin[k] = i0 + k < n ? src[at + k] : 0.0f;
+        }
+        const Words q = philox(t, kTagSirNoise, r, m, key0, key1);
+        double e[4];
+        box_muller(q.x0, q.x1, e[0], e[1]);
+        box_muller(q.x2, q.x3, e[2], e[3]);
+        const double zt = z[(uint64_t)r * zld + t];
+        float xo[4], wo[4];
 #pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-        const double xp = (double)xin[k];
-        const double xn = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + drift + sigma_v * e[k];
-        xo[k] = (float)xn;
-        const double xd = (double)xo[k];
-        const double res = zt - xd * xd / 20.0;
-        wo[k] = (float)exp(-0.5 * res * res);
-    }
-    if (full) {
-        *reinterpret_cast<float4*>(x + at) = make_float4(xo[0], xo[1], xo[2], xo[3]);
-        *reinterpret_cast<float4*>(w + at) = make_float4(wo[0], wo[1], wo[2], wo[3]);
-    } else {
-        for (uint32_t k = 0; k < 4 && i0 + k < n; ++k) {
-            x[at + k] = xo[k];
-            w[at + k] = wo[k];
+        for (uint32_t k = 0; k < 4; ++k) {
+            const double xp = (double)xin[k];
+            const double xn = xp / 2.0 + 25.0 * xp / (1.0 + xp * xp) + drift + sigma_v * e[k];
+            xo[k] = (float)xn;
+            const double xd = (double)xo[k];
+            const double res = zt - xd * xd / 20.0;
+            wo[k] = (float)exp(-0.5 * res * res);
+        }
+        if (full) {
+            *reinterpret_cast<float4*>(x + at) = make_float4(xo[0], xo[1], xo[2], xo[3]);
+            const float4 w4 = make_float4(wo[0], wo[1], wo[2], wo[3]);
+            *reinterpret_cast<float4*>(w + at) = w4;
+            if (mirror && (n & 3u) == 0) {
+                *reinterpret_cast<float4*>(mirror + i0) = w4;
+                *reinterpret_cast<float4*>(mirror + n + i0) = w4;
+            } else if (mirror) {
+#pragma unroll
+                for (uint32_t k = 0; k < 4; ++k) {
+                    mirror[i0 + k] = wo[k];
+                    mirror[n + i0 + k] = wo[k];
+                }
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) fold(wo[k], mx, s, bad);
+        } else {
+            for (uint32_t k = 0; k < 4 && i0 + k < n; ++k) {
+                x[at + k] = xo[k];
+                w[at + k] = wo[k];
+                if (mirror) {
+                    mirror[i0 + k] = wo[k];
+                    mirror[n + i0 + k] = wo[k];
+                }
+                fold(wo[k], mx, s, bad);
+            }
+        }
+        if (mirror && i0 < kMirrorPad) {
+            // the padding after the two copies: M[2n + k] = w_{k mod n}
+            for (uint32_t k = 0; k < 4 && i0 + k < n; ++k)
+                for (uint32_t c = i0 + k; c < kMirrorPad; c += n) mirror[2ull * n + c] = wo[k];
         }
     }
+    block_reduce(mx, s, bad);
+    if (threadIdx.x == 0) parts[part_base + blockIdx.x] = Partial{s, mx, bad};
 }
 
 // Stage 3, first pass: the fp64 sum of particles [c * kMeanChunk, ...) of run
@@ -209,8 +248,7 @@ struct mgp_sir_filter {
     int32_t* st_hist = nullptr;
     double* mean_part = nullptr;
     FilterDev* d_fd = nullptr;
-    RTile* d_rt = nullptr;
-    uint32_t n_rt = 0;
+    uint32_t nparts = 0;      // stage-1 blocks (and resampler partials) per run
     Partial* d_parts = nullptr;
     mgp_stats* d_stats = nullptr;
     uint32_t* d_qcount = nullptr;
@@ -286,13 +324,14 @@ int enqueue_predict(mgp_sir_filter* f, uint32_t t, hipStream_t s)
     const uint32_t quads = (f->n + 3u) / 4u;
     const dim3 grid((quads + kSirThreads - 1) / kSirThreads, f->R);
     hipLaunchKernelGGL(k_sir_predict_update, grid, dim3(kSirThreads), 0, s, f->xbar, f->x, f->w, f->z, f->d_stats,
-                       f->d_fd, f->ld, f->zld, f->n, t, drift, f->sigma_v, f->key0, f->key1);
+                       f->d_fd, f->d_parts, f->ld, f->zld, f->n, t, drift, f->sigma_v, f->key0, f->key1);
     return check_launch("SIR predict/update");
 }
 
 int enqueue_resample(mgp_sir_filter* f, hipStream_t s)
 {
-    return enqueue_batch(f->cfg.variant, f->shape, f->d_fd, f->R, f->d_rt, f->n_rt, f->d_parts, f->d_stats, f->d_lt,
+    // stage 1 wrote the partials and the mirror: finalize and accept loop only
+    return enqueue_batch(f->cfg.variant, f->shape, f->d_fd, f->R, nullptr, 0u, f->d_parts, f->d_stats, f->d_lt,
                          f->grid, f->d_qoff, f->d_qcount, (uint32_t)f->nxcd, 1u, s);
 }
 
@@ -399,9 +438,9 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->grid = (uint32_t)table.size();
 
     // ---- one allocation: particles, weights, histories, resampler tables
-    const uint32_t nparts = reduce_blocks(f->n);
-    const uint32_t chunk = reduce_chunk(f->n, nparts);
-    f->n_rt = nparts * f->R;
+    // one partial per stage-1 block of kSirThreads threads x 4 particles
+    const uint32_t nparts = (f->n + 4u * kSirThreads - 1u) / (4u * kSirThreads);
+    f->nparts = nparts;
     const uint32_t offs_cap = B_fixed ? B_fixed : f->cfg.b_max;
     const size_t rows = (size_t)f->R * f->ld;
     size_t off = 0;
@@ -420,8 +459,7 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     const size_t o_sh = take((size_t)f->R * f->T * sizeof(int32_t));
     const size_t o_mp = take((size_t)f->R * f->nchunks * sizeof(double));
     const size_t o_fd = take((size_t)f->R * sizeof(FilterDev));
-    const size_t o_rt = take((size_t)f->n_rt * sizeof(RTile));
-    const size_t o_parts = take((size_t)f->n_rt * sizeof(Partial));
+    const size_t o_parts = take((size_t)f->R * nparts * sizeof(Partial));
     const size_t o_stats = take((size_t)f->R * sizeof(mgp_stats));
     const size_t o_q = take(sizeof(uint32_t) * 2 * (kMaxXcd + 1));
     const size_t o_lt = take(table.size() * sizeof(LTile));
@@ -442,7 +480,6 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->st_hist = reinterpret_cast<int32_t*>(f->dmem + o_sh);
     f->mean_part = reinterpret_cast<double*>(f->dmem + o_mp);
     f->d_fd = reinterpret_cast<FilterDev*>(f->dmem + o_fd);
-    f->d_rt = reinterpret_cast<RTile*>(f->dmem + o_rt);
     f->d_parts = reinterpret_cast<Partial*>(f->dmem + o_parts);
     f->d_stats = reinterpret_cast<mgp_stats*>(f->dmem + o_stats);
     f->d_qcount = reinterpret_cast<uint32_t*>(f->dmem + o_q);
@@ -450,8 +487,6 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->d_lt = reinterpret_cast<LTile*>(f->dmem + o_lt);
 
     std::vector<FilterDev> fd(f->R);
-    std::vector<RTile> rt;
-    rt.reserve(f->n_rt);
     const uint32_t n_w = f->cfg.partition_bytes / 4u;
     for (uint32_t r = 0; r < f->R; ++r) {
         FilterDev& F = fd[r];
@@ -472,15 +507,13 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
         F.stream_id = r;
         F.part_base = r * nparts;
         F.nparts = nparts;
-        F.chunk = chunk;
+        F.chunk = 4u * kSirThreads;
         F.n_w = n_w;
         F.n_part = (uint32_t)(((uint64_t)f->n + n_w - 1u) / n_w);
         F.vec = (!mego || f->n % 4u == 0) ? 1u : 0u;  // rows are 256-byte aligned
         F.rows4 = 0;
-        for (uint32_t c = 0; c < nparts; ++c) rt.push_back(RTile{r, c});
     }
     if (hipMemcpyAsync(f->d_fd, fd.data(), fd.size() * sizeof(FilterDev), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(f->d_rt, rt.data(), rt.size() * sizeof(RTile), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(f->d_lt, table.data(), table.size() * sizeof(LTile), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(f->d_qoff, qoff.data(), qoff.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemsetAsync(f->z, 0, (size_t)f->R * f->zld * sizeof(double), s) != hipSuccess ||
