@@ -329,9 +329,9 @@ int mgp_server_destroy(mgp_server* server);
  * for a pair (a, b), u1 = (a + 1) 2^-32, u2 = b 2^-32, and the even particle
  * takes sqrt(-2 ln u1) cos(2 pi u2), the odd one sqrt(-2 ln u1) sin(2 pi u2).
  * The resample of step t uses key seed + t * 2^32 and stream r. A run whose
- * weights all underflow to 0 at a step (status MGP_EWEIGHTS) keeps its
- * predicted particles for that step (x_bar_t = x_t) and its estimate is their
- * mean. Results are pure functions of (x_bar_0, z, config): identical for
+ * weights all underflow to 0 at a step (status MGP_EWEIGHTS; its ancestors
+ * are -1) keeps its predicted particles for that step: stage 3 writes
+ * x_bar_t = x_t and its estimate is their mean. Results are pure functions of (x_bar_0, z, config): identical for
  * every launch shape and for graph or stage-by-stage execution, up to the
  * ~1e-16 relative rounding order of the fp64 mean. */
 typedef struct mgp_sir_config {

@@ -28,8 +28,9 @@
 // with stream r.
 //
 // A run whose weights all underflow to zero at some step (its resample
-// reports MGP_EWEIGHTS) keeps its predicted particles for that step: its
-// estimate is their mean and the next prediction starts from them.
+// reports MGP_EWEIGHTS, with -1 ancestors) keeps its predicted particles for
+// that step: stage 3 copies them into x_bar, its estimate is their mean, and
+// the next prediction starts from them.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -164,16 +165,21 @@ __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float*
 }
 
 // Stage 3, first pass: the fp64 sum of particles [c * kMeanChunk, ...) of run
-// blockIdx.y (of x_bar, or of x when that run's resample failed).
+// blockIdx.y: of x_bar, or, when that run's resample failed, of x, which is
+// then also copied into x_bar.
 template <bool Vec>
-__global__ __launch_bounds__(kReduceThreads) void k_sir_mean_partial(const float* __restrict__ xbar,
+__global__ __launch_bounds__(kReduceThreads) void k_sir_mean_partial(float* __restrict__ xbar,
                                                                      const float* __restrict__ x,
                                                                      const mgp_stats* __restrict__ stats,
                                                                      uint64_t ld, uint32_t n, uint32_t nchunks,
                                                                      double* __restrict__ partial)
 {
     const uint32_t r = blockIdx.y, c = blockIdx.x;
-    const float* src = (stats[r].status == MGP_OK ? xbar : x) + (uint64_t)r * ld;
+    // a run whose resample failed keeps its predicted particles: x_bar = x
+    // (the resampler left -1 ancestors and NaN rows there)
+    const bool failed = stats[r].status != MGP_OK;
+    const float* src = (failed ? x : xbar) + (uint64_t)r * ld;
+    float* dst = xbar + (uint64_t)r * ld;
     const uint32_t start = c * kMeanChunk;
     const uint32_t stop = min(n, start + kMeanChunk);
     double s = 0.0;
@@ -182,6 +188,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_sir_mean_partial(const float
         const uint32_t stop4 = start + ((stop - start) & ~3u);
         for (uint32_t j = start + 4u * threadIdx.x; j < stop4; j += 4u * kReduceThreads) {
             const float4 v = *reinterpret_cast<const float4*>(src + j);
+            if (failed) *reinterpret_cast<float4*>(dst + j) = v;
             s += (double)v.x;
             s += (double)v.y;
             s += (double)v.z;
@@ -189,7 +196,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_sir_mean_partial(const float
         }
         i = stop4 + threadIdx.x;
     }
-    for (; i < stop; i += kReduceThreads) s += (double)src[i];
+    for (; i < stop; i += kReduceThreads) {
+        const float v = src[i];
+        if (failed) dst[i] = v;
+        s += (double)v;
+    }
     float mx = 0.0f;
     uint32_t bad = 0;
     block_reduce(mx, s, bad);

@@ -130,6 +130,26 @@ def test_graph_equals_stage_by_stage_and_launch_shapes(env):
         f.close()
 
 
+@pytest.mark.parametrize("R,n", [(1, 1), (2, 3), (3, 5), (1, 63), (2, 1025), (1, 8192 + 7)])
+def test_small_and_ragged_sizes(env, R, n):
+    """Sizes that leave partial quads, partial stage-1 blocks and a single
+    particle (whose mirror padding repeats it 2048 times)."""
+    torch, mgp = env
+    T = 6
+    _, z, x0 = problem(R, n, T)
+    for variant in ("megopolis", "c2"):
+        f = make(env, R, n, T, z, x0, variant=variant, B=7)
+        f.run()
+        est, bs, st = f.results()
+        gxb = f.copy("xbar").cpu().numpy()
+        f.close()
+        for r in range(R):
+            oe, ob, ost, oxb = oracle.sir_filter(x0[r], z[r], variant, 7, SEED, r)
+            np.testing.assert_array_equal(st[r], ost)
+            np.testing.assert_array_equal(gxb[r], oxb, err_msg=f"{variant} R={R} n={n} run {r}")
+            np.testing.assert_allclose(est[r], oe, rtol=0, atol=4 * n * 2.0 ** -53 * 40.0 + 1e-12)
+
+
 def test_degenerate_step_keeps_predicted_particles(env):
     torch, mgp = env
     R, n, T = 3, 2048, 6
