@@ -68,7 +68,11 @@ def lib():
                                           ctypes.c_uint32, ctypes.c_uint32, _u32p, _i32p, _u64p]
         L.mgp_oracle_resample.restype = ctypes.c_int
         L.mgp_oracle_resample_m.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
-                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u32p, _i32p]
+                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u32p,
+                                            _i32p]
+        L.mgp_oracle_megopolis_index_s.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                                   ctypes.c_uint32]
+        L.mgp_oracle_megopolis_index_s.restype = ctypes.c_uint32
         L.mgp_oracle_resample_m.restype = ctypes.c_int
         L.mgp_oracle_resample_subset.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
                                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u32p,
@@ -127,8 +131,10 @@ def offsets(seed: int, stream_id: int, n: int, B: int) -> np.ndarray:
     return o[:B]
 
 
-def megopolis_index(i: int, o: int, n: int) -> int:
-    return int(lib().mgp_oracle_megopolis_index(i, o, n))
+def megopolis_index(i: int, o: int, n: int, segment: int = 32) -> int:
+    if segment == 32:
+        return int(lib().mgp_oracle_megopolis_index(i, o, n))
+    return int(lib().mgp_oracle_megopolis_index_s(i, o, n, segment))
 
 
 @dataclass
@@ -185,13 +191,14 @@ def resample(w: np.ndarray, variant, B: int, seed: int, stream_id: int = 0, part
 
 
 def resample_m(w: np.ndarray, m: int, variant, B: int, seed: int, stream_id: int = 0,
-               partition_bytes: int = 128) -> np.ndarray:
-    """M != N: m ancestors from the n = len(w) weighted inputs."""
+               partition_bytes: int = 128, segment: int = 32) -> np.ndarray:
+    """M != N: m ancestors from the n = len(w) weighted inputs (m = n: the
+    usual resample); `segment` is the Megopolis segment width, 32 or 64."""
     w = np.ascontiguousarray(w, dtype=np.float32)
     anc = np.empty(m, dtype=np.int32)
     scratch = np.zeros(max(B, 1), dtype=np.uint32)
     rc = lib().mgp_oracle_resample_m(_ptr(w, _f32p), w.size, m, _variant(variant), B, seed, stream_id,
-                                     partition_bytes, _ptr(scratch, _u32p), _ptr(anc, _i32p))
+                                     partition_bytes, segment, _ptr(scratch, _u32p), _ptr(anc, _i32p))
     if rc:
         raise OracleError(rc, "mgp_oracle_resample_m")
     return anc

@@ -150,14 +150,21 @@ void mgp_oracle_offsets(uint64_t seed, uint32_t stream_id, uint32_t n, uint32_t 
 }
 
 /* Megopolis candidate index (Algorithm 5): aligned particle index, plus the
- * aligned part of the offset, plus the offset inside the 32-wide segment,
- * all taken mod N. */
+ * aligned part of the offset, plus the offset inside the segment, all taken
+ * mod N. The paper's segment is 32 wide (its warp); `segment` generalises it
+ * (a power of two, e.g. 64 for a 64-lane wavefront). */
+uint32_t mgp_oracle_megopolis_index_s(uint32_t i, uint32_t o, uint32_t n, uint32_t segment)
+{
+    uint64_t i_aligned = (uint64_t)i - (uint64_t)(i % segment);
+    uint64_t o_aligned = (uint64_t)o - (uint64_t)(o % segment);
+    uint64_t o_unaligned = ((uint64_t)i + (uint64_t)o) % segment;
+    return (uint32_t)((i_aligned + o_aligned + o_unaligned) % (uint64_t)n);
+}
+
+/* The paper's segment is its 32-thread warp. */
 uint32_t mgp_oracle_megopolis_index(uint32_t i, uint32_t o, uint32_t n)
 {
-    uint64_t i_aligned = (uint64_t)i - (uint64_t)(i % 32u);
-    uint64_t o_aligned = (uint64_t)o - (uint64_t)(o % 32u);
-    uint64_t o_unaligned = ((uint64_t)i + (uint64_t)o) % 32u;
-    return (uint32_t)((i_aligned + o_aligned + o_unaligned) % (uint64_t)n);
+    return mgp_oracle_megopolis_index_s(i, o, n, 32u);
 }
 
 /* Metropolis-C1/C2 candidate index (Algorithms 3 and 4): a partition p of
@@ -179,8 +186,8 @@ static uint32_t partition_index(uint32_t n, uint32_t n_w, uint32_t part_word, ui
  * the particle's chain started from (i itself when inputs and outputs are
  * the same particles; i mod N when M != N): the Megopolis segment arithmetic
  * uses it, while the random draws and the C1/C2 group use i. */
-static uint32_t proposal(int variant, uint32_t n, uint32_t n_w, uint64_t seed, uint32_t stream_id,
-                         const uint32_t* offsets, uint32_t i, uint32_t pos, uint32_t b)
+static uint32_t proposal(int variant, uint32_t n, uint32_t n_w, uint32_t segment, uint64_t seed,
+                         uint32_t stream_id, const uint32_t* offsets, uint32_t i, uint32_t pos, uint32_t b)
 {
     uint32_t x[4], px[4];
     switch (variant) {
@@ -196,7 +203,7 @@ static uint32_t proposal(int variant, uint32_t n, uint32_t n_w, uint64_t seed, u
         draw_words(seed, OR_TAG_J, stream_id, i, b / 4u, x);
         return partition_index(n, n_w, px[b % 4u], x[b % 4u]);
     default: /* OR_MEGOPOLIS */
-        return mgp_oracle_megopolis_index(pos, offsets[b], n);
+        return mgp_oracle_megopolis_index_s(pos, offsets[b], n, segment);
     }
 }
 
@@ -214,12 +221,12 @@ static int check_common(int variant, int32_t n, uint32_t partition_bytes)
  * j with the ratio test u <= w_j / w_k written as the fp32 product
  * u * w_k <= w_j (ties accept). Returns the ancestor k. */
 static int32_t run_chain(const float* w, uint32_t n, int variant, uint32_t B, uint64_t seed,
-                         uint32_t stream_id, uint32_t n_w, const uint32_t* offsets, uint32_t i,
-                         uint32_t pos, uint64_t* accepts)
+                         uint32_t stream_id, uint32_t n_w, uint32_t segment, const uint32_t* offsets,
+                         uint32_t i, uint32_t pos, uint64_t* accepts)
 {
     uint32_t k = pos;
     for (uint32_t b = 0; b < B; ++b) {
-        uint32_t j = proposal(variant, n, n_w, seed, stream_id, offsets, i, pos, b);
+        uint32_t j = proposal(variant, n, n_w, segment, seed, stream_id, offsets, i, pos, b);
         float u = mgp_oracle_draw_u(seed, stream_id, i, b);
         float p = u * w[k];
         if (p <= w[j]) {
@@ -246,7 +253,7 @@ int mgp_oracle_resample(const float* w, int32_t n, int variant, uint32_t B, uint
     if (accepts) *accepts = 0;
     uint32_t n_w = partition_bytes / 4u;
     for (uint32_t i = 0; i < (uint32_t)n; ++i)
-        ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w,
+        ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, 32u,
                                  offsets_scratch, i, i, accepts);
     return OR_OK;
 }
@@ -257,22 +264,24 @@ int mgp_oracle_resample(const float* w, int32_t n, int variant, uint32_t B, uint
  * offsets o_b ~ U{0, n-1} and candidates are taken over the n inputs, with
  * the Megopolis segment arithmetic on the start position; the u and j draws
  * and the C1/C2 group floor(i / 32) are those of output i. With m == n this
- * is mgp_oracle_resample. */
+ * is mgp_oracle_resample. `segment` is the Megopolis segment width (32, the
+ * paper's, or 64). */
 int mgp_oracle_resample_m(const float* w, int32_t n, int32_t m, int variant, uint32_t B, uint64_t seed,
-                          uint32_t stream_id, uint32_t partition_bytes, uint32_t* offsets_scratch,
-                          int32_t* ancestors)
+                          uint32_t stream_id, uint32_t partition_bytes, uint32_t segment,
+                          uint32_t* offsets_scratch, int32_t* ancestors)
 {
     int rc = check_common(variant, n, partition_bytes);
     if (rc) return rc;
     if (m < 1) return OR_EINVAL;
+    if (segment != 32u && segment != 64u) return OR_EINVAL;
     if (variant == OR_MEGOPOLIS) {
         if (!offsets_scratch) return OR_EINVAL;
         mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
     }
     uint32_t n_w = partition_bytes / 4u;
     for (uint32_t i = 0; i < (uint32_t)m; ++i)
-        ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, offsets_scratch, i,
-                                 i % (uint32_t)n, NULL);
+        ancestors[i] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, segment, offsets_scratch,
+                                 i, i % (uint32_t)n, NULL);
     return OR_OK;
 }
 
@@ -291,7 +300,7 @@ int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t 
     uint32_t n_w = partition_bytes / 4u;
     for (int32_t c = 0; c < count; ++c) {
         if (idx[c] < 0 || idx[c] >= n) return OR_EINVAL;
-        ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w,
+        ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, 32u,
                                  offsets_scratch, (uint32_t)idx[c], (uint32_t)idx[c], NULL);
     }
     return OR_OK;
@@ -312,7 +321,7 @@ int mgp_oracle_trace(int32_t n, int variant, uint32_t B, uint64_t seed, uint32_t
     }
     uint32_t n_w = partition_bytes / 4u;
     for (uint32_t b = 0; b < B; ++b) {
-        j_out[b] = proposal(variant, (uint32_t)n, n_w, seed, stream_id, offsets_scratch,
+        j_out[b] = proposal(variant, (uint32_t)n, n_w, 32u, seed, stream_id, offsets_scratch,
                             (uint32_t)i, (uint32_t)i, b);
         u_out[b] = mgp_oracle_draw_u(seed, stream_id, (uint32_t)i, b);
     }
