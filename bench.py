@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant sweep at N=2^22")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--no-sir", action="store_true", help="skip the SIR filter section")
+    ap.add_argument("--no-segment64", action="store_true", help="skip the 64-wide-segment Megopolis step")
     ap.add_argument("--sir-table", action="store_true",
                     help="the SIR section for every (variant, B) row of Table 2 instead of Megopolis B=16 only")
     ap.add_argument("--sir-mc-runs", type=int, default=50)
@@ -71,7 +72,7 @@ def parse():
     return ap.parse_args()
 
 
-def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup, seed0):
+def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup, seed0, segment=32):
     """Runs warmup + steps; returns wall ms per step and per-step event times."""
     stream = torch.cuda.current_stream()
     n = w.numel()
@@ -81,10 +82,10 @@ def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup,
         seed = seed0 + s
         if e:
             e[0].record(stream)
-        r.compute_B(w, variant, epsilon=eps, seed=seed)
+        r.compute_B(w, variant, epsilon=eps, seed=seed, segment=segment)
         if e:
             e[1].record(stream)
-        r.resample_prepared(w, variant, epsilon=eps, seed=seed, out=anc)
+        r.resample_prepared(w, variant, epsilon=eps, seed=seed, out=anc, segment=segment)
         if e:
             e[2].record(stream)
         mgp.gather(states, anc, out=out)
@@ -527,6 +528,14 @@ def main():
                                 "p99_ms": pct(per_m["total"], 99)}
         result["speedup_vs_metropolis"] = ms_m / ms
         log(f"[bench] metropolis: {ms_m:.3f} ms/step, loop {lm:.3f} ms -> speedup {ms_m / ms:.2f}x")
+
+    if args.variant == "megopolis" and not args.no_segment64:
+        ms_s, per_s = timed_steps(torch, mgp, r, w, states, anc, out, "megopolis", args.eps, 5, 1, 0, segment=64)
+        ls = float(np.mean(per_s["loop"]))
+        result["megopolis_segment64"] = {"ms_per_step": ms_s, "loop_ms": ls,
+                                         "effective_GBs": loop_bytes / (ls * 1e-3) / 1e9,
+                                         "workload": "the same step with 64-wide Megopolis segments"}
+        log(f"[bench] megopolis, 64-wide segments: {ms_s:.3f} ms/step, loop {ls:.3f} ms")
 
     if not args.no_batched:
         log("[bench] batched: 512 filters")

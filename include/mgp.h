@@ -60,7 +60,8 @@ typedef struct mgp_params {
     uint32_t stream_id;       /* Philox counter word 2: 0 for a single filter, filter / request id otherwise */
     uint32_t partition_bytes; /* C1/C2 partition size P_size in bytes, multiple of 4; 0 means 128 */
     uint32_t b_max;           /* upper clamp for a derived B, and the limit for an explicit B; 0 means 65536 */
-    uint32_t reserved;        /* must be 0 */
+    uint32_t segment;         /* Megopolis segment width: 32 (the paper's warp; 0 means 32) or 64 (the gfx950
+                                 wavefront); single-filter entry points only */
 } mgp_params;
 
 /* Written on the device by mgp_resample / mgp_compute_B (48 bytes). */

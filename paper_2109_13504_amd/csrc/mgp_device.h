@@ -117,12 +117,14 @@ __device__ __forceinline__ uint32_t word(const Words& x, uint32_t r)
 }
 
 // Megopolis candidate: aligned segment of i plus aligned part of o, rotated by
-// (i + o) mod 32 inside the segment; the sum is <= i + o <= 2N - 2, so one
+// (i + o) mod S inside the segment (S = seg_mask + 1, 32 or 64, a wave-uniform
+// value); the sum is <= i + o <= 2N - 2, so one
 // conditional subtraction is the mod N. min(j, j - n) in unsigned arithmetic
 // picks j - n exactly when j >= n (n <= 2^31).
-__device__ __forceinline__ uint32_t megopolis_index(uint32_t i_aligned, uint32_t i_low, uint32_t o, uint32_t n)
+__device__ __forceinline__ uint32_t megopolis_index(uint32_t i_aligned, uint32_t i_low, uint32_t o, uint32_t n,
+                                                    uint32_t seg_mask)
 {
-    const uint32_t j = i_aligned + (o & ~(kSegment - 1u)) + ((i_low + o) & (kSegment - 1u));
+    const uint32_t j = i_aligned + (o & ~seg_mask) + ((i_low + o) & seg_mask);
     const uint32_t jm = j - n;
     return jm < j ? jm : j;
 }
@@ -158,6 +160,7 @@ struct LoopParams {
     uint32_t stream_id;
     uint32_t n_w;     // C1/C2: weights per partition
     uint32_t n_part;  // C1/C2: number of partitions, ceil(n / n_w)
+    uint32_t seg_mask = kSegment - 1u;  // Megopolis: segment width - 1
 };
 
 // o_b, clamped below n so that a workspace not written by this call's
@@ -185,8 +188,8 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
     const float* __restrict__ w = P.w;
     uint32_t k = pos;
     float wk = load_weight<Narrow>(w, pos);
-    const uint32_t i_aligned = pos & ~(kSegment - 1u);
-    const uint32_t i_low = pos & (kSegment - 1u);
+    const uint32_t i_aligned = pos & ~P.seg_mask;
+    const uint32_t i_low = pos & P.seg_mask;
     const uint32_t group = i / kSegment;
 
     uint32_t c1_part = 0;
@@ -208,7 +211,7 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
             const uint32_t b = q * U + s;
             uint32_t j;
             if constexpr (V == kMegopolis) {
-                j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n);
+                j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n, P.seg_mask);
             } else {
                 if (s % 4 == 0) {
                     const uint32_t blk = q * (U / 4) + s / 4;
@@ -249,7 +252,7 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
         if (r5 == 0u) ub = u_block(philox(b / 5u, kTagU, P.stream_id, i, P.key0, P.key1));
         uint32_t j;
         if constexpr (V == kMegopolis) {
-            j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n);
+            j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n, P.seg_mask);
         } else {
             if (r4 == 0u) {
                 jb = philox(b / 4u, kTagJ, P.stream_id, i, P.key0, P.key1);
@@ -291,7 +294,8 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
 // ancestor. Each thread carries P particles i0 + BT p (BT = block size);
 // they share i mod 32, so all P candidates of a step are the slot-0
 // candidate plus BT p, and the P loads differ only in their immediate byte
-// offset (4 BT p).
+// offset (4 BT p). The segment width S = seg_mask + 1 (32 or 64) divides BT,
+// so the P particles of a thread also share i mod S.
 // Byte offsets must fit 32 bits: 4 (2n + kMirrorPad) < 2^32.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMirrorPad = 2048;             // >= 256 P + 32 for P <= 4
@@ -300,13 +304,14 @@ constexpr uint32_t kMirrorMaxN = (1u << 29) - 4096;
 template <int P, int BT = 256>
 __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ M, const uint32_t* __restrict__ offs,
                                                        uint32_t n, uint32_t B, uint32_t key0, uint32_t key1,
-                                                       uint32_t stream_id, uint32_t i0, uint32_t (&anc_out)[P])
+                                                       uint32_t stream_id, uint32_t i0, uint32_t (&anc_out)[P],
+                                                       uint32_t seg_mask = kSegment - 1u)
 {
-    static_assert(BT % 64 == 0 && BT * P + kSegment <= kMirrorPad, "particles of a thread must fit the padding");
+    static_assert(BT % 64 == 0 && BT * P + 64 <= kMirrorPad, "particles of a thread must fit the padding");
     static_assert(4 * BT * (P - 1) < 4096, "the immediate offset of the last particle must fit 12 bits");
     constexpr uint32_t kStrideBytes = 4u * BT;  // particle p sits BT particles after p - 1
-    const uint32_t ia4 = (i0 & ~(kSegment - 1u)) * 4u;
-    const uint32_t il4 = (i0 & (kSegment - 1u)) * 4u;
+    const uint32_t ia4 = (i0 & ~seg_mask) * 4u;
+    const uint32_t il4 = (i0 & seg_mask) * 4u;
     uint32_t kk[P];  // ancestor as the slot-0 byte offset into M
     float wk[P];
 #pragma unroll
@@ -322,8 +327,8 @@ __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ 
         for (uint32_t s = 0; s < 5; ++s) {
             uint32_t o = offs[q * 5u + s];
             o = o < n ? o : n - 1u;
-            const uint32_t oa4 = (o & ~(kSegment - 1u)) * 4u;
-            const uint32_t t4 = (il4 + (o & (kSegment - 1u)) * 4u) & ((kSegment - 1u) * 4u);
+            const uint32_t oa4 = (o & ~seg_mask) * 4u;
+            const uint32_t t4 = (il4 + (o & seg_mask) * 4u) & (seg_mask * 4u);
             const uint32_t voff = ia4 | t4;
             const char* base = M + oa4;
 #pragma unroll
@@ -352,8 +357,8 @@ __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ 
         for (uint32_t b = nblk * 5u; b < B; ++b) {
             uint32_t o = offs[b];
             o = o < n ? o : n - 1u;
-            const uint32_t oa4 = (o & ~(kSegment - 1u)) * 4u;
-            const uint32_t t4 = (il4 + (o & (kSegment - 1u)) * 4u) & ((kSegment - 1u) * 4u);
+            const uint32_t oa4 = (o & ~seg_mask) * 4u;
+            const uint32_t t4 = (il4 + (o & seg_mask) * 4u) & (seg_mask * 4u);
             const uint32_t voff = ia4 | t4;
             const char* base = M + oa4;
             const uint32_t r = b - nblk * 5u;

@@ -64,6 +64,7 @@ struct Params {
     uint32_t stream_id;
     uint32_t partition_bytes;
     uint32_t b_max;
+    uint32_t segment = 32;  // Megopolis segment width, 32 or 64
 };
 
 int fail(int code, const char* fmt, ...);

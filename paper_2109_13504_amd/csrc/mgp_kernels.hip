@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
                                                            const uint32_t* __restrict__ offsets, uint32_t key0,
                                                            uint32_t key1, uint32_t stream_id, uint32_t n_w,
                                                            uint32_t n_part, uint32_t tag, uint32_t b_cap,
-                                                           int32_t* __restrict__ anc)
+                                                           uint32_t seg_mask, int32_t* __restrict__ anc)
 {
     const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
     const uint32_t B = st->B;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
         anc[i] = -1;
         return;
     }
-    LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part};
+    LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part, seg_mask};
     // output i starts at input i mod n (i itself when m <= n)
     const uint32_t pos = i < n ? i : i % n;
     anc[i] = (int32_t)run_chain<V, Narrow>(P, i, pos);
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* 
                                                                    uint32_t m, const mgp_stats* __restrict__ st,
                                                                    const uint32_t* __restrict__ offsets,
                                                                    uint32_t key0, uint32_t key1, uint32_t stream_id,
-                                                                   uint32_t tag, uint32_t b_cap,
+                                                                   uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
                                                                    int32_t* __restrict__ anc)
 {
     const uint32_t i0 = blockIdx.x * (kLoopThreads * P) + threadIdx.x;
@@ -126,7 +126,8 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* 
     // every lane runs, also past m (m <= n here): the mirror's padding keeps
     // those loads in bounds, and only real outputs store
     uint32_t k[P];
-    megopolis_mirror_chain<P>(reinterpret_cast<const char*>(mirror), offsets, n, B, key0, key1, stream_id, i0, k);
+    megopolis_mirror_chain<P>(reinterpret_cast<const char*>(mirror), offsets, n, B, key0, key1, stream_id, i0, k,
+                              seg_mask);
 #pragma unroll
     for (int p = 0; p < P; ++p)
         if (i0 + kLoopThreads * p < m) anc[i0 + kLoopThreads * p] = (int32_t)k[p];
@@ -205,7 +206,9 @@ int normalize_params(const mgp_params* in, Params* out)
     out->stream_id = in->stream_id;
     out->partition_bytes = in->partition_bytes ? in->partition_bytes : 128u;
     out->b_max = in->b_max ? in->b_max : kDefaultBMax;
-    if (in->reserved != 0) return fail(MGP_EINVAL, "params.reserved must be 0");
+    out->segment = in->segment ? in->segment : 32u;
+    if (out->segment != 32u && out->segment != 64u)
+        return fail(MGP_EINVAL, "segment must be 32 or 64 (got %u)", in->segment);
     if (out->partition_bytes < 4u || out->partition_bytes % 4u != 0u)
         return fail(MGP_EINVAL, "partition_bytes must be a positive multiple of 4 (got %u)", out->partition_bytes);
     if (out->b_max > kBMaxLimit) return fail(MGP_ERANGE, "b_max %u above the limit %u", out->b_max, kBMaxLimit);
@@ -268,14 +271,15 @@ int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool ma
 template <int V>
 static void launch_loop(bool narrow, dim3 grid, hipStream_t s, const float* w, uint32_t n, uint32_t m,
                         const mgp_stats* st, const uint32_t* offs, uint32_t k0, uint32_t k1, uint32_t sid,
-                        uint32_t n_w, uint32_t n_part, uint32_t tag, uint32_t b_cap, int32_t* anc)
+                        uint32_t n_w, uint32_t n_part, uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
+                        int32_t* anc)
 {
     if (narrow)
         hipLaunchKernelGGL((k_resample<V, true>), grid, dim3(kLoopThreads), 0, s, w, n, m, st, offs, k0, k1, sid,
-                           n_w, n_part, tag, b_cap, anc);
+                           n_w, n_part, tag, b_cap, seg_mask, anc);
     else
         hipLaunchKernelGGL((k_resample<V, false>), grid, dim3(kLoopThreads), 0, s, w, n, m, st, offs, k0, k1, sid,
-                           n_w, n_part, tag, b_cap, anc);
+                           n_w, n_part, tag, b_cap, seg_mask, anc);
 }
 
 int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream)
@@ -295,26 +299,27 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
     const bool narrow = n <= (1u << 30);
     const uint32_t tag = call_tag(n, p.variant, p.seed, p.stream_id);
     const uint32_t cap = p.b_max;
+    const uint32_t seg_mask = p.segment - 1u;
     if (uses_mirror(n, p.variant) && m <= n) {
         constexpr int P = kMegopolisPPT;
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
         const dim3 g((m + kLoopThreads * P - 1u) / (kLoopThreads * P));
         hipLaunchKernelGGL((k_megopolis_mirror<P>), g, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs, k0, k1,
-                           p.stream_id, tag, cap, anc);
+                           p.stream_id, tag, cap, seg_mask, anc);
         return check_launch("megopolis kernel");
     }
     switch (p.variant) {
     case kMetropolis:
-        launch_loop<kMetropolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kMetropolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
         break;
     case kC1:
-        launch_loop<kC1>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kC1>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
         break;
     case kC2:
-        launch_loop<kC2>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kC2>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
         break;
     default:
-        launch_loop<kMegopolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, anc);
+        launch_loop<kMegopolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
         break;
     }
     return check_launch("resample kernel");

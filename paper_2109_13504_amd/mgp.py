@@ -30,7 +30,7 @@ class MgpError(RuntimeError):
 class mgp_params(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("B", ctypes.c_uint32), ("epsilon", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("partition_bytes", ctypes.c_uint32),
-                ("b_max", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("b_max", ctypes.c_uint32), ("segment", ctypes.c_uint32)]
 
 
 class mgp_stats(ctypes.Structure):
@@ -187,10 +187,10 @@ def _check(rc: int, func: str) -> int:
 
 
 def make_params(variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
-                partition_bytes: int = 128, b_max: int = 0) -> mgp_params:
+                partition_bytes: int = 128, b_max: int = 0, segment: int = 32) -> mgp_params:
     v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     return mgp_params(v, int(B), float(epsilon), int(seed) & (2**64 - 1), int(stream_id), int(partition_bytes),
-                      int(b_max), 0)
+                      int(b_max), int(segment))
 
 
 # ---------------------------------------------------------------------------
@@ -415,46 +415,50 @@ class Resampler:
         self.stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=self.device)
 
     def resample(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
-                 stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+                 stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None,
+                 segment: int = 32):
         _require_weights(w)
         torch = _torch()
         n = w.numel()
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=w.device)
-        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_resample(w.data_ptr(), n, p, out.data_ptr(), self.stats.data_ptr(), self.workspace.data_ptr(),
                      self.ws_bytes, current_stream() if stream is None else stream)
         return out
 
     def resample_m(self, w, m: int, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
-                   stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+                   stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None,
+                 segment: int = 32):
         """m ancestors from the n = w.numel() weighted inputs (M != N)."""
         _require_weights(w)
         torch = _torch()
         if out is None:
             out = torch.empty(int(m), dtype=torch.int32, device=w.device)
-        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_resample_m(w.data_ptr(), w.numel(), int(m), p, out.data_ptr(), self.stats.data_ptr(),
                        self.workspace.data_ptr(), self.ws_bytes, current_stream() if stream is None else stream)
         return out
 
     def compute_B(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
-                  stream_id: int = 0, partition_bytes: int = 128, stream: int | None = None) -> None:
+                  stream_id: int = 0, partition_bytes: int = 128, stream: int | None = None,
+                  segment: int = 32) -> None:
         """Reduction, B and offsets only (asynchronous; read last_stats() after a sync)."""
         _require_weights(w)
-        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_compute_B(w.data_ptr(), w.numel(), p, self.stats.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
                       current_stream() if stream is None else stream)
 
     def resample_prepared(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
-                          stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None):
+                          stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None,
+                 segment: int = 32):
         """The accept loop only, after compute_B with the same arguments."""
         _require_weights(w)
         torch = _torch()
         n = w.numel()
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=w.device)
-        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_resample_prepared(w.data_ptr(), n, p, out.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
                               current_stream() if stream is None else stream)
         return out
@@ -464,10 +468,10 @@ class Resampler:
 
 
 def resample(w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
-             partition_bytes: int = 128, b_max: int = 0):
+             partition_bytes: int = 128, b_max: int = 0, segment: int = 32):
     """One-shot resample of a device weight vector; returns (ancestors, stats dict)."""
     r = Resampler(w.numel(), b_max, w.device)
-    anc = r.resample(w, variant, B, epsilon, seed, stream_id, partition_bytes)
+    anc = r.resample(w, variant, B, epsilon, seed, stream_id, partition_bytes, segment=segment)
     return anc, r.last_stats()
 
 

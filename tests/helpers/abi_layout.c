@@ -12,7 +12,7 @@ int main(void)
 {
     printf("{\n");
     S(mgp_params); F(mgp_params, variant); F(mgp_params, B); F(mgp_params, epsilon); F(mgp_params, seed);
-    F(mgp_params, stream_id); F(mgp_params, partition_bytes); F(mgp_params, b_max); F(mgp_params, reserved);
+    F(mgp_params, stream_id); F(mgp_params, partition_bytes); F(mgp_params, b_max); F(mgp_params, segment);
     S(mgp_stats); F(mgp_stats, w_sum); F(mgp_stats, ratio); F(mgp_stats, b_raw); F(mgp_stats, w_max); F(mgp_stats, B);
     F(mgp_stats, clamped); F(mgp_stats, status); F(mgp_stats, n); F(mgp_stats, tag);
     S(mgp_filter_desc); F(mgp_filter_desc, w_dev); F(mgp_filter_desc, n); F(mgp_filter_desc, B);

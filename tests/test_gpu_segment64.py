@@ -1,0 +1,79 @@
+"""Megopolis with 64-wide segments on the GPU (params.segment = 64) against
+the oracle, bit for bit: the mirrored kernel (m <= n) and the generic one
+(m > n), ragged n, B from epsilon, the split compute_B / prepared loop.
+Quality at N = 2^20: MSE/N next to the 32-wide segments' (no printed values
+for 64-wide segments exist: parity unpinned; the check is that the two
+widths give close MSE/N, both far below Metropolis's)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.metrics import QualityAccumulator
+from paper_2109_13504_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2109_13504_amd import mgp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mgp.lib()
+    return torch, torch.device("cuda:0"), mgp
+
+
+@pytest.mark.parametrize("n", [4096, 5003, 1 << 18])
+def test_segment64_matches_oracle(env, n):
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 3.0, 4)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    for m in (n, n // 2 + 1, 2 * n + 5):
+        anc = r.resample_m(wd, m, "megopolis", epsilon=0.01, seed=90 + m, stream_id=3, segment=64)
+        torch.cuda.synchronize()
+        B = r.last_stats()["B"]
+        ref = oracle.resample_m(w, m, "megopolis", B, 90 + m, stream_id=3, segment=64)
+        np.testing.assert_array_equal(anc.cpu().numpy(), ref, err_msg=f"n={n} m={m}")
+    # the split path and the one-shot call agree
+    r.compute_B(wd, "megopolis", epsilon=0.01, seed=5, segment=64)
+    a = r.resample_prepared(wd, "megopolis", epsilon=0.01, seed=5, segment=64).cpu()
+    b = r.resample(wd, "megopolis", epsilon=0.01, seed=5, segment=64).cpu()
+    assert torch.equal(a, b)
+    if n <= 16:
+        return
+    # and differ from 32-wide segments (a different candidate map)
+    c = r.resample(wd, "megopolis", epsilon=0.01, seed=5).cpu()
+    assert not torch.equal(b, c)
+
+
+def test_bad_segment_rejected(env):
+    torch, dev, mgp = env
+    r = mgp.Resampler(64)
+    with pytest.raises(mgp.MgpError) as e:
+        r.resample(torch.ones(64, device=dev), "megopolis", B=3, segment=48)
+    assert e.value.code == mgp.MGP_EINVAL
+
+
+def test_segment64_quality_close_to_32(env):
+    torch, dev, mgp = env
+    n = 1 << 20
+    r = mgp.Resampler(n)
+    rows = []
+    for y in range(5):
+        mse = {}
+        for seg in (32, 64):
+            per = []
+            for q in range(2):
+                w = inputs.gaussian_weights(n, float(y), 60 + q)
+                wd = torch.from_numpy(w).to(dev)
+                acc = QualityAccumulator(w)
+                for k in range(4):
+                    acc.add(r.resample(wd, "megopolis", epsilon=0.01, seed=700 + 10 * q + k, segment=seg).cpu().numpy())
+                per += [se / n for se in acc.se_list]
+            mse[seg] = float(np.mean(per))
+        rows.append((y, mse[32], mse[64]))
+        assert abs(mse[64] - mse[32]) < 0.05 * mse[32] + 0.01, (y, mse)
+        assert mse[64] < 0.8
+    print("MSE/N by y (32-wide, 64-wide):", [(y, round(a, 4), round(b, 4)) for y, a, b in rows])
