@@ -46,8 +46,8 @@ def source_hash() -> str:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--variant", default="megopolis", choices=["megopolis", "metropolis", "c1", "c2"])
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--y", type=float, default=4.0)
