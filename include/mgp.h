@@ -368,6 +368,10 @@ typedef struct mgp_sir_buffers {
 
 typedef struct mgp_sir_filter mgp_sir_filter;
 
+/* A filter holds one set of buffers: its calls must be ordered (issued on one
+ * stream, or synchronised between streams). Calls on different filters are
+ * independent. */
+
 /* Allocates the filter's device memory (particles, weights, the per-run
  * resampler tables, the estimate history) and, with use_graph, captures the T
  * steps into one hipGraph. Measurements start as 0 (set them with
@@ -391,7 +395,8 @@ int mgp_sir_resample(mgp_sir_filter* filter, int32_t t, void* stream);
 int mgp_sir_estimate(mgp_sir_filter* filter, int32_t t, void* stream);
 
 /* Steps 1..T, right after mgp_sir_reset: one graph launch with use_graph,
- * else 6 T plain launches. */
+ * else 5 T plain launches (stage 1; finalize and accept loop; two for the
+ * mean). */
 int mgp_sir_run(mgp_sir_filter* filter, void* stream);
 
 /* Copies the history of the steps run so far (R x T each, row-major, host;
