@@ -438,7 +438,7 @@ def serving_section(torch, mgp, inputs, n_requests, streams=4, max_batch=8, max_
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library resamples on one GPU (the multi-GPU design is not built)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
