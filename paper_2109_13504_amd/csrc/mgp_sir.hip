@@ -18,8 +18,9 @@
 //   stage 2  the batched resampler from its finalize step on (B, offsets,
 //            validation), then the accept loop with the fused gather
 //            x_bar_i = x_{k_i}, one filter per run;
-//   stage 3  k_sir_mean_partial + k_sir_mean_final: x_hat_t = sum(x_bar) / n
-//            in fp64, in a fixed order that depends on n only.
+//   stage 3  k_sir_mean_block + k_sir_mean_final: x_hat_t = sum(x_bar) / n
+//            in fp64, in a fixed order that depends on n only; in a graph of
+//            steps the next step's stage 1 computes the block sums instead.
 // The noise v of particle i in run r at step t is sqrt(10) times a standard
 // normal from Box-Muller in its two-output form: Philox4x32-10 at counter
 // (t, 5, r, floor(i / 4)) under the filter's seed gives two word pairs, pair
@@ -50,7 +51,6 @@ namespace mgp {
 
 constexpr uint32_t kTagSirNoise = 5u;
 constexpr uint32_t kSirThreads = 256;
-constexpr uint32_t kMeanChunk = 8192;  // particles per stage-3 partial sum
 constexpr uint32_t kRowAlign = 64;     // floats: every run's row starts 256-byte aligned
 constexpr double kPi = 3.14159265358979323846;
 
@@ -75,13 +75,16 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& even,
 // resampler's per-weight work while the weights are in registers: the
 // block's partial (fp32 max, fp64 sum, validity) for the finalize step, and
 // for Megopolis the mirror M[i] = M[i + n] = w_i (plus M[2n + k] = w_{k mod n}
-// for k < kMirrorPad).
-__global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float* __restrict__ xbar, float* x,
+// for k < kMirrorPad). With mean_part it also writes the block's sum of its
+// input particles, the previous step's x_bar, in the order of k_sir_mean_block,
+// so that a graph of steps needs no separate pass for stage 3.
+__global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(float* __restrict__ xbar, float* x,
                                                                     float* __restrict__ w,
                                                                     const double* __restrict__ z,
                                                                     const mgp_stats* __restrict__ stats,
                                                                     FilterDev* __restrict__ fd,
-                                                                    Partial* __restrict__ parts, uint64_t ld,
+                                                                    Partial* __restrict__ parts,
+                                                                    double* __restrict__ mean_part, uint64_t ld,
                                                                     uint32_t zld, uint32_t n, uint32_t t,
                                                                     double drift, double sigma_v, uint32_t key0,
                                                                     uint32_t key1)
@@ -94,13 +97,14 @@ __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float*
     if (blockIdx.x == 0 && threadIdx.x == 0) fd[r].key1 = key1 + t;
     const uint32_t i0 = 4u * m;
     float mx = 0.0f;
-    double s = 0.0;
+    double s = 0.0, prev_sum = 0.0;
     uint32_t bad = 0;
     if (i0 < n) {
         const uint64_t at = (uint64_t)r * ld + i0;  // rows are 256-byte aligned
         const bool full = i0 + 4u <= n;
         // a run whose last resample failed continues from its predicted particles
-        const float* src = stats[r].status == MGP_OK ? xbar : x;
+        const bool failed = stats[r].status != MGP_OK;
+        const float* src = failed ? x : xbar;
         float xin[4];
         if (full) {
             const float4 v = *reinterpret_cast<const float4*>(src + at);
@@ -111,6 +115,14 @@ __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float*
         } else {
 #pragma unroll
             for (uint32_t k = 0; k < 4; ++k) xin[k] = i0 + k < n ? src[at + k] : 0.0f;
+        }
+        if (mean_part) {
+            // the previous step's estimate: its x_bar (x for a failed run,
+            // which then also becomes its x_bar), summed as mean_block does
+            for (uint32_t k = 0; k < 4 && i0 + k < n; ++k) {
+                prev_sum += (double)xin[k];
+                if (failed) xbar[at + k] = xin[k];
+            }
         }
         const Words q = philox(t, kTagSirNoise, r, m, key0, key1);
         double e[4];
@@ -162,55 +174,70 @@ __global__ __launch_bounds__(kSirThreads) void k_sir_predict_update(const float*
     }
     block_reduce(mx, s, bad);
     if (threadIdx.x == 0) parts[part_base + blockIdx.x] = Partial{s, mx, bad};
+    if (mean_part) {
+        __syncthreads();  // block_reduce's shared slots are reused
+        float dmx = 0.0f;
+        uint32_t dbad = 0;
+        block_reduce(dmx, prev_sum, dbad);
+        if (threadIdx.x == 0) mean_part[(uint64_t)r * gridDim.x + blockIdx.x] = prev_sum;
+    }
 }
 
-// Stage 3, first pass: the fp64 sum of particles [c * kMeanChunk, ...) of run
-// blockIdx.y: of x_bar, or, when that run's resample failed, of x, which is
-// then also copied into x_bar.
-template <bool Vec>
-__global__ __launch_bounds__(kReduceThreads) void k_sir_mean_partial(float* __restrict__ xbar,
-                                                                     const float* __restrict__ x,
-                                                                     const mgp_stats* __restrict__ stats,
-                                                                     uint64_t ld, uint32_t n, uint32_t nchunks,
-                                                                     double* __restrict__ partial)
+// Stage 3, first pass: the fp64 sum of each group of 1024 particles
+// [1024 g, 1024 g + 1024) of run blockIdx.y, four consecutive particles per
+// thread in index order, then the block reduction: the decomposition of
+// k_sir_predict_update, so that both give the same sums. A block covers
+// kMeanGroups groups and issues all their loads before reducing. It sums
+// x_bar, or, when that run's resample failed, x, which it then copies into
+// x_bar.
+constexpr uint32_t kMeanGroups = 8;
+
+__global__ __launch_bounds__(kSirThreads) void k_sir_mean_block(float* __restrict__ xbar,
+                                                                const float* __restrict__ x,
+                                                                const mgp_stats* __restrict__ stats, uint64_t ld,
+                                                                uint32_t n, uint32_t nparts,
+                                                                double* __restrict__ partial)
 {
-    const uint32_t r = blockIdx.y, c = blockIdx.x;
-    // a run whose resample failed keeps its predicted particles: x_bar = x
-    // (the resampler left -1 ancestors and NaN rows there)
+    const uint32_t r = blockIdx.y;
     const bool failed = stats[r].status != MGP_OK;
     const float* src = (failed ? x : xbar) + (uint64_t)r * ld;
     float* dst = xbar + (uint64_t)r * ld;
-    const uint32_t start = c * kMeanChunk;
-    const uint32_t stop = min(n, start + kMeanChunk);
-    double s = 0.0;
-    uint32_t i = start + threadIdx.x;
-    if constexpr (Vec) {
-        const uint32_t stop4 = start + ((stop - start) & ~3u);
-        for (uint32_t j = start + 4u * threadIdx.x; j < stop4; j += 4u * kReduceThreads) {
-            const float4 v = *reinterpret_cast<const float4*>(src + j);
-            if (failed) *reinterpret_cast<float4*>(dst + j) = v;
-            s += (double)v.x;
-            s += (double)v.y;
-            s += (double)v.z;
-            s += (double)v.w;
+    float v[kMeanGroups][4];
+#pragma unroll
+    for (uint32_t g = 0; g < kMeanGroups; ++g) {
+        const uint32_t i0 = 4u * ((blockIdx.x * kMeanGroups + g) * kSirThreads + threadIdx.x);
+        if (i0 + 4u <= n) {
+            const float4 q = *reinterpret_cast<const float4*>(src + i0);  // rows are 256-byte aligned
+            v[g][0] = q.x;
+            v[g][1] = q.y;
+            v[g][2] = q.z;
+            v[g][3] = q.w;
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) v[g][k] = i0 + k < n ? src[i0 + k] : 0.0f;
         }
-        i = stop4 + threadIdx.x;
     }
-    for (; i < stop; i += kReduceThreads) {
-        const float v = src[i];
-        if (failed) dst[i] = v;
-        s += (double)v;
+    for (uint32_t g = 0; g < kMeanGroups; ++g) {
+        const uint32_t grp = blockIdx.x * kMeanGroups + g;
+        if (grp >= nparts) break;  // uniform across the block
+        const uint32_t i0 = 4u * (grp * kSirThreads + threadIdx.x);
+        double s = 0.0;
+        for (uint32_t k = 0; k < 4 && i0 + k < n; ++k) {
+            s += (double)v[g][k];
+            if (failed) dst[i0 + k] = v[g][k];
+        }
+        float mx = 0.0f;
+        uint32_t bad = 0;
+        block_reduce(mx, s, bad);
+        if (threadIdx.x == 0) partial[(uint64_t)r * nparts + grp] = s;
+        __syncthreads();  // block_reduce's shared slots are reused by the next group
     }
-    float mx = 0.0f;
-    uint32_t bad = 0;
-    block_reduce(mx, s, bad);
-    if (threadIdx.x == 0) partial[(uint64_t)r * nchunks + c] = s;
 }
 
 // Stage 3, second pass: x_hat_t = sum / n for run blockIdx.x, plus the B and
 // status of that run's resample at step t.
 __global__ __launch_bounds__(kReduceThreads) void k_sir_mean_final(const double* __restrict__ partial,
-                                                                   uint32_t nchunks, uint32_t n,
+                                                                   uint32_t nparts, uint32_t n,
                                                                    const mgp_stats* __restrict__ stats,
                                                                    double* __restrict__ est,
                                                                    uint32_t* __restrict__ b_hist,
@@ -219,7 +246,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_sir_mean_final(const double*
 {
     const uint32_t r = blockIdx.x;
     double s = 0.0;
-    for (uint32_t c = threadIdx.x; c < nchunks; c += kReduceThreads) s += partial[(uint64_t)r * nchunks + c];
+    for (uint32_t c = threadIdx.x; c < nparts; c += kReduceThreads) s += partial[(uint64_t)r * nparts + c];
     float mx = 0.0f;
     uint32_t bad = 0;
     block_reduce(mx, s, bad);
@@ -244,7 +271,6 @@ struct mgp_sir_filter {
     int nxcd = 1;
     uint32_t n = 0, R = 0, T = 0;
     uint64_t ld = 0;          // row stride (floats) of x, w, x_bar, ancestors
-    uint32_t nchunks = 0;     // stage-3 partials per run
     uint32_t zld = 0;         // T + 1
     uint32_t key0 = 0, key1 = 0;
     double sigma_v = 0.0;
@@ -329,13 +355,15 @@ void advance(mgp_sir_filter* f)
     }
 }
 
-int enqueue_predict(mgp_sir_filter* f, uint32_t t, hipStream_t s)
+// Stage 1 of step t; with with_mean it also writes the block sums of step
+// t - 1's estimate.
+int enqueue_predict(mgp_sir_filter* f, uint32_t t, bool with_mean, hipStream_t s)
 {
     const double drift = 8.0 * cos(1.2 * (double)t);
-    const uint32_t quads = (f->n + 3u) / 4u;
-    const dim3 grid((quads + kSirThreads - 1) / kSirThreads, f->R);
+    const dim3 grid(f->nparts, f->R);
     hipLaunchKernelGGL(k_sir_predict_update, grid, dim3(kSirThreads), 0, s, f->xbar, f->x, f->w, f->z, f->d_stats,
-                       f->d_fd, f->d_parts, f->ld, f->zld, f->n, t, drift, f->sigma_v, f->key0, f->key1);
+                       f->d_fd, f->d_parts, with_mean ? f->mean_part : nullptr, f->ld, f->zld, f->n, t, drift,
+                       f->sigma_v, f->key0, f->key1);
     return check_launch("SIR predict/update");
 }
 
@@ -346,31 +374,37 @@ int enqueue_resample(mgp_sir_filter* f, hipStream_t s)
                          f->grid, f->d_qoff, f->d_qcount, (uint32_t)f->nxcd, 1u, s);
 }
 
-int enqueue_estimate(mgp_sir_filter* f, uint32_t t, hipStream_t s)
+// The per-run combine of stage 3 for step t: x_hat_t = (sum of the block
+// sums) / n, and the history of B and status.
+int enqueue_mean_final(mgp_sir_filter* f, uint32_t t, hipStream_t s)
 {
-    const dim3 grid(f->nchunks, f->R);
-    if (f->ld % 4u == 0)
-        hipLaunchKernelGGL(k_sir_mean_partial<true>, grid, dim3(kReduceThreads), 0, s, f->xbar, f->x, f->d_stats, f->ld,
-                           f->n, f->nchunks, f->mean_part);
-    else
-        hipLaunchKernelGGL(k_sir_mean_partial<false>, grid, dim3(kReduceThreads), 0, s, f->xbar, f->x, f->d_stats,
-                           f->ld, f->n, f->nchunks, f->mean_part);
-    int rc = check_launch("SIR mean (partial sums)");
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_sir_mean_final, dim3(f->R), dim3(kReduceThreads), 0, s, f->mean_part, f->nchunks, f->n,
+    hipLaunchKernelGGL(k_sir_mean_final, dim3(f->R), dim3(kReduceThreads), 0, s, f->mean_part, f->nparts, f->n,
                        f->d_stats, f->est, f->b_hist, f->st_hist, f->T, t);
     return check_launch("SIR mean (final)");
 }
 
+int enqueue_estimate(mgp_sir_filter* f, uint32_t t, hipStream_t s)
+{
+    const dim3 grid((f->nparts + kMeanGroups - 1) / kMeanGroups, f->R);
+    hipLaunchKernelGGL(k_sir_mean_block, grid, dim3(kSirThreads), 0, s, f->xbar, f->x, f->d_stats, f->ld, f->n,
+                       f->nparts, f->mean_part);
+    int rc = check_launch("SIR mean (block sums)");
+    if (rc) return rc;
+    return enqueue_mean_final(f, t, s);
+}
+
+// Steps 1..T. Stage 1 of step t + 1 reads step t's x_bar anyway, so it also
+// produces step t's block sums; the combine for step t then runs before
+// step t + 1's resample rewrites the stats. Only step T has a separate pass.
 int enqueue_steps(mgp_sir_filter* f, hipStream_t s)
 {
     for (uint32_t t = 1; t <= f->T; ++t) {
-        int rc = enqueue_predict(f, t, s);
+        int rc = enqueue_predict(f, t, t > 1, s);
+        if (!rc && t > 1) rc = enqueue_mean_final(f, t - 1, s);
         if (!rc) rc = enqueue_resample(f, s);
-        if (!rc) rc = enqueue_estimate(f, t, s);
         if (rc) return rc;
     }
-    return MGP_OK;
+    return enqueue_estimate(f, f->T, s);
 }
 
 int capture(mgp_sir_filter* f)
@@ -425,7 +459,6 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->T = (uint32_t)cfg->steps;
     f->zld = f->T + 1;
     f->ld = ((uint64_t)f->n + kRowAlign - 1) / kRowAlign * kRowAlign;
-    f->nchunks = (f->n + kMeanChunk - 1) / kMeanChunk;
     f->key0 = (uint32_t)cfg->seed;
     f->key1 = (uint32_t)(cfg->seed >> 32);
     f->sigma_v = sqrt(10.0);
@@ -468,7 +501,7 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     const size_t o_est = take((size_t)f->R * f->T * sizeof(double));
     const size_t o_bh = take((size_t)f->R * f->T * sizeof(uint32_t));
     const size_t o_sh = take((size_t)f->R * f->T * sizeof(int32_t));
-    const size_t o_mp = take((size_t)f->R * f->nchunks * sizeof(double));
+    const size_t o_mp = take((size_t)f->R * nparts * sizeof(double));
     const size_t o_fd = take((size_t)f->R * sizeof(FilterDev));
     const size_t o_parts = take((size_t)f->R * nparts * sizeof(Partial));
     const size_t o_stats = take((size_t)f->R * sizeof(mgp_stats));
@@ -572,7 +605,7 @@ int mgp_sir_predict_update(mgp_sir_filter* f, int32_t t, void* stream)
     clear_error();
     if (!f) return fail(MGP_EINVAL, "filter is NULL");
     int rc = check_stage(f, t, 1);
-    if (!rc) rc = enqueue_predict(f, (uint32_t)t, static_cast<hipStream_t>(stream));
+    if (!rc) rc = enqueue_predict(f, (uint32_t)t, false, static_cast<hipStream_t>(stream));
     if (!rc) advance(f);
     return rc;
 }
