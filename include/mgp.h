@@ -12,8 +12,8 @@
  * Conventions for every entry point:
  *   - Pointers named *_dev are device pointers (HBM of the current device);
  *     everything else is host memory. The caller owns every buffer it passes;
- *     the library allocates only inside batch-plan and server objects and
- *     frees that memory when the object is destroyed.
+ *     the library allocates only inside batch-plan, server and SIR-filter
+ *     objects and frees that memory when the object is destroyed.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls are asynchronous on that stream, like HIP's own: a return of
  *     MGP_OK means the work was enqueued.
@@ -23,7 +23,8 @@
  *     negative, or all weights zero) are reported in mgp_stats.status as
  *     MGP_EWEIGHTS; every ancestor is then written as -1.
  *   - Results are pure functions of (weights, variant, B, seed, stream_id,
- *     partition_bytes): identical across calls, launch shapes and batches.
+ *     partition_bytes, segment): identical across calls, launch shapes and
+ *     batches.
  */
 #ifndef MGP_H
 #define MGP_H
@@ -49,7 +50,7 @@ typedef enum mgp_variant {
     MGP_METROPOLIS = 0, /* Algorithm 2: j ~ U{0, N-1} per particle and step */
     MGP_C1 = 1,         /* Algorithm 3: one partition per 32-particle group for all steps */
     MGP_C2 = 2,         /* Algorithm 4: a new partition per group at every step */
-    MGP_MEGOPOLIS = 3   /* Algorithm 5: B offsets shared by every particle, wrapped 32-segments */
+    MGP_MEGOPOLIS = 3   /* Algorithm 5: B offsets shared by every particle, wrapped segments (32 wide) */
 } mgp_variant;
 
 typedef struct mgp_params {
