@@ -165,7 +165,7 @@ typedef struct mgp_batch_config {
     uint32_t partition_bytes;    /* C1/C2; 0 means 128 */
     uint32_t b_max;              /* per-filter clamp / limit of B; 0 means 65536 */
     int32_t block_threads;       /* 64, 128 or 256; 0: autotune */
-    int32_t particles_per_thread;/* 1, 2 or 4 (Megopolis; others use 1); 0: autotune */
+    int32_t particles_per_thread;/* Megopolis: 1, 2, 4 or 8 (8 with 64 or 128 threads); others: 1; 0: autotune */
     int32_t schedule;            /* 1: one block per tile; 2: persistent blocks on per-XCD queues; 0: autotune */
     int32_t use_graph;           /* 1: one hipGraph launch per run; 0: three plain launches */
     const char* tune_cache;      /* autotuner cache file (read and updated), or NULL */
