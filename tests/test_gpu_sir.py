@@ -150,6 +150,26 @@ def test_small_and_ragged_sizes(env, R, n):
             np.testing.assert_allclose(est[r], oe, rtol=0, atol=4 * n * 2.0 ** -53 * 40.0 + 1e-12)
 
 
+def test_benchmark_path_100_steps(env):
+    """The bench's configuration on a smaller population: Megopolis, B = 16,
+    all 100 steps as one graph launch in the default launch shape, 2 runs of
+    2^16 particles; every estimate and the final particles against the
+    oracle."""
+    torch, mgp = env
+    R, n, T = 2, 1 << 16, 100
+    _, z, x0 = problem(R, n, T)
+    f = make(env, R, n, T, z, x0, variant="megopolis", B=16)
+    f.run()
+    est, bs, st = f.results()
+    gxb = f.copy("xbar").cpu().numpy()
+    f.close()
+    for r in range(R):
+        oe, ob, ost, oxb = oracle.sir_filter(x0[r], z[r], "megopolis", 16, SEED, r)
+        np.testing.assert_array_equal(st[r], ost)
+        np.testing.assert_array_equal(gxb[r], oxb, err_msg=f"run {r}")
+        np.testing.assert_allclose(est[r], oe, rtol=0, atol=4 * n * 2.0 ** -53 * 40.0)
+
+
 def test_degenerate_step_keeps_predicted_particles(env):
     torch, mgp = env
     R, n, T = 3, 2048, 6
