@@ -327,6 +327,44 @@ def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20,
             "runs": R, "n": n, "steps": T, "rows": out}
 
 
+# Table 3 (Megopolis), y = 4 column, seconds on the Tesla K40m, by N
+K40M_MEGOPOLIS_Y4 = {1 << 15: 5.170e-4, 1 << 16: 8.173e-4, 1 << 17: 0.0014, 1 << 18: 0.0027, 1 << 19: 0.0055,
+                     1 << 20: 0.0113, 1 << 21: 0.0233, 1 << 22: 0.0478}
+
+
+def n_sweep_section(torch, mgp, inputs):
+    """Megopolis resample time (reduction, B, offsets, accept loop; no
+    gather) against N = 2^15 .. 2^26, Gaussian-likelihood weights y = 4,
+    eps = 0.01, median of 5; the paper's Table 3 y = 4 column as context."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = {}
+    for ln in range(15, 27):
+        n = 1 << ln
+        w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
+        anc = torch.empty(n, dtype=torch.int32, device=dev)
+        r = mgp.Resampler(n)
+        times = []
+        for k in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            r.resample(w, "megopolis", epsilon=0.01, seed=k, out=anc)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if k:
+                times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        B = r.last_stats()["B"]
+        k40 = K40M_MEGOPOLIS_Y4.get(n)
+        rows[f"2^{ln}"] = {"ms": ms, "B": B, "particles_per_s": n / (ms * 1e-3),
+                           "effective_GBs": 4.0 * n * (B + 2) / (ms * 1e-3) / 1e9,
+                           "k40m_ms": k40 * 1e3 if k40 else None}
+        del w, anc, r
+    return {"workload": "Megopolis, Gaussian-likelihood weights y=4, eps=0.01; resample = reduction + B + accept loop "
+                        "(no gather); median of 5; k40m_ms from Table 3", "rows": rows}
+
+
 def m_neq_n_section(torch, mgp, inputs):
     """M != N resampling (Section 8's D-PMC remark): Megopolis, B from
     eps = 0.01 on Gaussian-likelihood weights with y = 4, N inputs -> M
@@ -547,6 +585,9 @@ def main():
     if not args.no_sweep:
         log("[bench] per-variant sweep at N=2^22")
         result["paper_sweep"] = sweep_section(torch, mgp, inputs)
+        log("[bench] N sweep")
+        result["n_sweep"] = n_sweep_section(torch, mgp, inputs)
+        log("[bench] " + ", ".join(f"{k}: {v['ms']:.3f} ms" for k, v in result["n_sweep"]["rows"].items()))
         log("[bench] M != N")
         result["m_neq_n"] = m_neq_n_section(torch, mgp, inputs)
         log(f"[bench] M != N: {result['m_neq_n']['runs']}")
