@@ -380,4 +380,78 @@ __device__ __forceinline__ void megopolis_mirror_chain(const char* __restrict__ 
     }
 }
 
+// Megopolis over the mirror, one particle per thread, with the candidate
+// weights of D steps (D a multiple of 5) loaded before the first of them is
+// used. The candidates do not depend on the accept results, so one round
+// trip to memory serves D steps; for small n, where too few waves are in
+// flight to hide the latency of the B/5 rounds of the chain above, this cuts
+// the number of round trips by D/5. The arithmetic and the random draws are
+// those of megopolis_mirror_chain, so the ancestors are identical.
+template <int D>
+__device__ __forceinline__ uint32_t megopolis_mirror_chain_deep(const char* __restrict__ M,
+                                                                const uint32_t* __restrict__ offs, uint32_t n,
+                                                                uint32_t B, uint32_t key0, uint32_t key1,
+                                                                uint32_t stream_id, uint32_t i, uint32_t seg_mask)
+{
+    static_assert(D % 5 == 0, "a round covers whole blocks of five u draws");
+    const uint32_t ia4 = (i & ~seg_mask) * 4u;
+    const uint32_t il4 = (i & seg_mask) * 4u;
+    uint32_t kk = i * 4u;
+    float wk = *reinterpret_cast<const float*>(M + i * 4u);
+    // steps [0, B5) in rounds of D, then whole blocks of 5, then the rest
+    const uint32_t nrnd = B / D;
+    for (uint32_t q = 0; q < nrnd; ++q) {
+        float wj[D];
+        uint32_t jb[D];
+#pragma unroll
+        for (uint32_t s = 0; s < D; ++s) {
+            uint32_t o = offs[q * D + s];
+            o = o < n ? o : n - 1u;
+            const uint32_t oa4 = (o & ~seg_mask) * 4u;
+            const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
+            wj[s] = *reinterpret_cast<const float*>(M + oa4 + voff);
+            jb[s] = voff + oa4;
+        }
+#pragma unroll
+        for (uint32_t g = 0; g < D / 5; ++g) {
+            const UBlock ub = u_block(philox(q * (D / 5) + g, kTagU, stream_id, i, key0, key1));
+#pragma unroll
+            for (uint32_t s = 0; s < 5; ++s) {
+                const float prod = ub.u[s] * wk;
+                const bool acc = prod <= wj[g * 5 + s];
+                kk = acc ? jb[g * 5 + s] : kk;
+                wk = acc ? wj[g * 5 + s] : wk;
+            }
+        }
+    }
+    for (uint32_t b0 = nrnd * D; b0 < B; b0 += 5u) {
+        const uint32_t cnt = B - b0 < 5u ? B - b0 : 5u;
+        float wj[5];
+        uint32_t jb[5];
+#pragma unroll
+        for (uint32_t s = 0; s < 5; ++s) {
+            if (s < cnt) {
+                uint32_t o = offs[b0 + s];
+                o = o < n ? o : n - 1u;
+                const uint32_t oa4 = (o & ~seg_mask) * 4u;
+                const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
+                wj[s] = *reinterpret_cast<const float*>(M + oa4 + voff);
+                jb[s] = voff + oa4;
+            }
+        }
+        const UBlock ub = u_block(philox(b0 / 5u, kTagU, stream_id, i, key0, key1));
+#pragma unroll
+        for (uint32_t s = 0; s < 5; ++s) {
+            if (s < cnt) {
+                const float prod = ub.u[s] * wk;
+                const bool acc = prod <= wj[s];
+                kk = acc ? jb[s] : kk;
+                wk = acc ? wj[s] : wk;
+            }
+        }
+    }
+    const uint32_t k = kk / 4u;
+    return k >= n ? k - n : k;
+}
+
 }  // namespace mgp

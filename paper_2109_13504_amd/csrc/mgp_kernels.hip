@@ -133,6 +133,34 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* 
         if (i0 + kLoopThreads * p < m) anc[i0 + kLoopThreads * p] = (int32_t)k[p];
 }
 
+// Megopolis over the mirrored weights for small n: one particle per thread,
+// kDeepSteps candidate loads per round trip (megopolis_mirror_chain_deep).
+// Used for m <= kDeepMaxM outputs, where the four-particle kernel leaves too
+// few waves in flight to hide its round trips.
+constexpr int kDeepSteps = 20;
+constexpr uint32_t kDeepMaxM = 1u << 18;
+
+__global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const float* __restrict__ mirror, uint32_t n,
+                                                                        uint32_t m, const mgp_stats* __restrict__ st,
+                                                                        const uint32_t* __restrict__ offsets,
+                                                                        uint32_t key0, uint32_t key1,
+                                                                        uint32_t stream_id, uint32_t tag,
+                                                                        uint32_t b_cap, uint32_t seg_mask,
+                                                                        int32_t* __restrict__ anc)
+{
+    const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
+    const uint32_t B = st->B;
+    const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    if (!ok) {
+        if (i < m) anc[i] = -1;
+        return;
+    }
+    // lanes past m run too (the mirror's padding keeps their loads in bounds)
+    const uint32_t k = megopolis_mirror_chain_deep<kDeepSteps>(reinterpret_cast<const char*>(mirror), offsets, n, B,
+                                                               key0, key1, stream_id, i, seg_mask);
+    if (i < m) anc[i] = (int32_t)k;
+}
+
 // ---------------------------------------------------------------------------
 // 4. Gather: out[i] = states[anc[i]] (rows of d fp32). With d % 4 == 0 and
 //    16-byte aligned rows every thread copies one float4; otherwise one
@@ -300,6 +328,13 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
     const uint32_t tag = call_tag(n, p.variant, p.seed, p.stream_id);
     const uint32_t cap = p.b_max;
     const uint32_t seg_mask = p.segment - 1u;
+    if (uses_mirror(n, p.variant) && m <= n && m <= kDeepMaxM) {
+        // few waves: deep prefetch per particle instead of four particles per thread
+        const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
+        hipLaunchKernelGGL(k_megopolis_mirror_deep, grid, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs, k0, k1,
+                           p.stream_id, tag, cap, seg_mask, anc);
+        return check_launch("megopolis kernel (small n)");
+    }
     if (uses_mirror(n, p.variant) && m <= n) {
         constexpr int P = kMegopolisPPT;
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
