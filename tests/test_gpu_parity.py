@@ -261,3 +261,23 @@ def test_split_compute_B_then_prepared_loop(torch_dev, mgp):
     r.compute_B(wd, "megopolis", epsilon=0.01, seed=77, stream_id=3)
     bad = r.resample_prepared(wd, "megopolis", epsilon=0.01, seed=78, stream_id=3).cpu().numpy()
     assert (bad == -1).all()
+
+
+@pytest.mark.parametrize("n", [1, 31, 257, 4101, 1 << 18, (1 << 18) + 1])
+def test_megopolis_small_n_rounds_and_tails(torch_dev, mgp, n):
+    """Megopolis up to 2^18 particles runs twenty steps per round of loads;
+    B below, at and past multiples of 20 and 5 exercise the rounds and the
+    tail. 2^18 + 1 is the first size on the four-particle kernel."""
+    torch, dev = torch_dev
+    w = inputs.gaussian_weights(n, 2.5, 17)
+    wd = _to_dev(torch, dev, w)
+    r = mgp.Resampler(n)
+    for B in (1, 4, 5, 19, 20, 21, 40, 41, 354):
+        got = r.resample(wd, "megopolis", B=B, seed=1000 + B, stream_id=2).cpu().numpy()
+        if n <= 4101:
+            np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", B, 1000 + B, stream_id=2),
+                                          err_msg=f"n={n} B={B}")
+        else:
+            idx = np.random.Generator(np.random.PCG64(B)).choice(n, 2000, replace=False).astype(np.int32)
+            ref = oracle.resample_subset(w, "megopolis", B, 1000 + B, idx, stream_id=2)
+            np.testing.assert_array_equal(got[idx], ref, err_msg=f"n={n} B={B}")
