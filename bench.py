@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--sir-table", action="store_true",
                     help="the SIR section for every (variant, B) row of Table 2 instead of Megopolis B=16 only")
     ap.add_argument("--sir-mc-runs", type=int, default=50)
+    ap.add_argument("--sir-bsweep", action="store_true",
+                    help="the SIR section for B in {5, 7, 10, 15, 20, 25, 30, 40} and every variant (Section 7's "
+                         "B study)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
     return ap.parse_args()
@@ -608,6 +611,8 @@ def main():
         rows = [("megopolis", 16)]
         if args.sir_table:
             rows = [(v, b) for b in (16, 32, 64) for v in ("megopolis", "metropolis", "c1", "c2")]
+        if args.sir_bsweep:
+            rows = [(v, b) for b in (5, 7, 10, 15, 20, 25, 30, 40) for v in ("megopolis", "metropolis", "c1", "c2")]
         log(f"[bench] SIR filter: {len(rows)} configuration(s)")
         result["sir"] = sir_section(torch, mgp, inputs, rows, mc_runs=args.sir_mc_runs)
 

@@ -5,7 +5,7 @@ trajectory). The trajectories are this repository's synthetic ones, not the
 paper's, so the RMSE is held to a band around the printed value; the
 orderings Table 2 shows are checked on the same trajectories: C1 with
 128-byte partitions is worse than Megopolis at B = 16, and Megopolis improves
-from B = 16 to B = 64."""
+from B = 16 to B = 64; so are the claims of the B study."""
 import json
 import os
 
@@ -58,3 +58,15 @@ def test_rmse_near_table2(rmse_of, variant, B):
 def test_table2_orderings(rmse_of):
     assert rmse_of("c1", 16) > rmse_of("megopolis", 16) + 0.05
     assert rmse_of("megopolis", 64) < rmse_of("megopolis", 16)
+
+
+def test_b_study_claims(rmse_of):
+    """Section 7's B study (its figures; no printed values): RMSE falls with
+    B with diminishing returns, C1 with 128-byte partitions needs about
+    B = 25 to match what Megopolis reaches at B = 10, and C1 stays above
+    Megopolis at equal B."""
+    mego = [rmse_of("megopolis", b) for b in (5, 10, 20, 40)]
+    assert mego[0] > mego[1] > mego[2] > mego[3]
+    assert mego[0] - mego[1] > mego[2] - mego[3]
+    assert abs(rmse_of("c1", 25) - rmse_of("megopolis", 10)) < 0.06
+    assert rmse_of("c1", 10) > rmse_of("megopolis", 10) + 0.05
