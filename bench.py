@@ -280,7 +280,7 @@ def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20,
     for variant, B in rows:
         key = f"{variant}-B{B}" if variant not in ("c1", "c2") else f"{variant}-ps128-B{B}"
         t0 = time.perf_counter()
-        f = mgp.SirFilter(R, n, T, variant=variant, B=B, seed=2021, use_graph=True)
+        f = mgp.SirFilter(R, n, T, variant=variant, B=B, epsilon=0.1, seed=2021, use_graph=True)
         create_s = time.perf_counter() - t0
         f.set_measurements(zr)
         # stage by stage, events around each stage (this pass also warms up)
@@ -319,6 +319,7 @@ def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20,
             "graph_ms_per_step": graph_ms[-1] / T, "particle_steps_per_s": steps / (graph_ms[-1] * 1e-3),
             "stage_by_stage_equals_graph": bool(np.array_equal(est, est2)),
             "degenerate_steps": int((st != 0).sum()), "create_s": create_s,
+            "mean_B": float(bs[st == 0].mean()) if (st == 0).any() else 0.0,
             "paper_k40m": {"resample_ratio": paper[0], "rmse": paper[1]} if paper else None,
         }
         log(f"[bench] sir {key}: RMSE {rmse:.3f} (paper {paper[1] if paper else '-'}), ratio {ratio:.3f} "
@@ -613,6 +614,7 @@ def main():
             rows = [(v, b) for b in (16, 32, 64) for v in ("megopolis", "metropolis", "c1", "c2")]
         if args.sir_bsweep:
             rows = [(v, b) for b in (5, 7, 10, 15, 20, 25, 30, 40) for v in ("megopolis", "metropolis", "c1", "c2")]
+            rows.append(("megopolis", 0))  # B from eq. (bcalc) with epsilon = 0.1 at every step
         log(f"[bench] SIR filter: {len(rows)} configuration(s)")
         result["sir"] = sir_section(torch, mgp, inputs, rows, mc_runs=args.sir_mc_runs)
 

@@ -70,3 +70,24 @@ def test_b_study_claims(rmse_of):
     assert mego[0] - mego[1] > mego[2] - mego[3]
     assert abs(rmse_of("c1", 25) - rmse_of("megopolis", 10)) < 0.06
     assert rmse_of("c1", 10) > rmse_of("megopolis", 10) + 0.05
+
+
+def test_epsilon_mode_mean_B_near_paper_baseline():
+    """Section 7 derives B per step from eq. (bcalc) with epsilon = 0.1 and
+    reports an average of 30 iterations at 2^20 particles."""
+    import torch
+
+    from paper_2109_13504_amd import mgp
+    n = GOLDEN["n"]
+    _, z = inputs.sir_truth(T, TRAJ)
+    zr = np.repeat(z, MC, axis=0)
+    x0 = inputs.sir_initial_particles_torch(TRAJ * MC, n, torch.device("cuda:0"))
+    f = mgp.SirFilter(TRAJ * MC, n, T, variant="megopolis", B=0, epsilon=0.1, seed=2021)
+    f.set_measurements(zr)
+    f.reset(x0)
+    f.run()
+    _, bs, st = f.results()
+    f.close()
+    assert (st == 0).all() and (bs >= 1).all()
+    assert 20.0 < bs.mean() < 40.0, bs.mean()
+    print("mean B at epsilon = 0.1:", bs.mean())
