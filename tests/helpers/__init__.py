@@ -154,3 +154,24 @@ def recurrence_P(n: int, ratio: float, B: int) -> float:
     for _ in range(B):
         P = 1.0 / n + P * (1.0 - ratio)
     return P
+
+
+def build_c_client() -> str:
+    """Compiles helpers/c_client.c, a plain C program that calls libmgp
+    through include/mgp.h and the HIP runtime's C API only, with gcc (the
+    library itself must already be built). Returns the executable's path."""
+    root = os.path.dirname(os.path.dirname(HERE))
+    src = os.path.join(HERE, "c_client.c")
+    exe = os.path.join(HERE, "c_client")
+    lib_dir = os.path.join(root, "paper_2109_13504_amd")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    if os.path.exists(exe) and os.path.getmtime(exe) >= max(os.path.getmtime(src),
+                                                            os.path.getmtime(os.path.join(lib_dir, "libmgp.so"))):
+        return exe
+    tmp = exe + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    "-I", os.path.join(root, "include"), "-I", os.path.join(rocm, "include"), "-o", tmp, src,
+                    "-L", lib_dir, "-lmgp", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+                    "-Wl,-rpath," + lib_dir, "-Wl,-rpath," + os.path.join(rocm, "lib")], check=True)
+    os.replace(tmp, exe)
+    return exe

@@ -91,3 +91,12 @@ def test_argument_errors_before_any_device_call(mgp):
 
 def test_version(mgp):
     assert mgp.mgp_version() >= 100
+
+
+def test_plain_c_client_builds_against_the_header_and_library():
+    """A C program using only include/mgp.h and the HIP runtime's C API
+    compiles without warnings and links against libmgp.so (it runs in the
+    GPU tests)."""
+    from helpers import build_c_client
+    exe = build_c_client()
+    assert os.access(exe, os.X_OK)
