@@ -125,7 +125,10 @@ int mgp_compute_B(const float* w_dev, int32_t n, const mgp_params* params, mgp_s
  * offsets that the preceding mgp_compute_B on this workspace left there.
  * params and n must equal that call's; the kernel checks a tag of
  * (n, variant, seed, stream_id) written by mgp_compute_B, and on a mismatch
- * (or invalid weights) writes -1 to every ancestor. */
+ * (or invalid weights) writes -1 to every ancestor. w_dev must hold the same
+ * weights as in that call: with MGP_MEGOPOLIS (n <= 2^29 - 4096) the loop
+ * reads the mirrored copy of them that mgp_compute_B left in the workspace,
+ * not w_dev, so weights changed in between are not seen. */
 int mgp_resample_prepared(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
                           void* workspace_dev, size_t workspace_bytes, void* stream);
 

@@ -142,6 +142,7 @@ struct mgp_server {
     uint32_t b_max = kDefaultBMax;
     uint32_t n_w = 32;
     int nxcd = 1;
+    int device = 0;  // the device current at create; the scheduler thread binds it
     int64_t max_particles = 1 << 24;
     uint32_t max_n = 1u << 22;
     uint32_t cap_f = 0, cap_rt = 0, cap_lt = 0;
@@ -317,7 +318,10 @@ void reap(mgp_server* s, Slot& sl)
 
 void scheduler(mgp_server* s)
 {
+    // the current device is per thread: bind the one the pool and streams
+    // were allocated on before any launch, copy or event query
     std::unique_lock<std::mutex> lk(s->mu);
+    if (!s->cfg.simulate && hipSetDevice(s->device) != hipSuccess) s->last_error = MGP_EHIP;
     int64_t batch_counter = 0;
     for (;;) {
         bool any_busy = false;
@@ -556,6 +560,7 @@ int mgp_server_create(const mgp_server_config* cfg, mgp_server** out)
             delete s;
             return fail(MGP_EHIP, "no HIP device");
         }
+        s->device = dev;
         s->nxcd = (cus >= 64 && cus % kMaxXcd == 0) ? kMaxXcd : 1;
         if (hipMalloc(&s->pool_base, cfg->hbm_budget) != hipSuccess) {
             s->pool_base = nullptr;
