@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=16, help="oracle runs every k-th particle's chain")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-filters section")
     ap.add_argument("--batch-runs", type=int, default=20)
+    ap.add_argument("--batch-shape", default=None,
+                    help="fixed batched launch shape 'block_threads,particles_per_thread,schedule' (default: autotuned)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant sweep at N=2^22")
     ap.add_argument("--serve-requests", type=int, default=5000)
@@ -134,10 +136,11 @@ def cpu_baseline(w_np, variant, eps, stride):
                       f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s"}
 
 
-def batched_section(torch, mgp, inputs, runs):
+def batched_section(torch, mgp, inputs, runs, shape=None):
     """512 filters, N_f = round(2^U(10, 18)), y_f ~ U[0, 4], D = 4, Megopolis:
     one graph launch per run against the same filters as 512 per-filter
-    launch sequences (reduce, finalize, loop, gather) issued from C."""
+    launch sequences (reduce, finalize, loop, gather) issued from C. `shape`
+    (block threads, particles per thread, schedule) skips the autotuner."""
     import tempfile
 
     import numpy as np
@@ -151,7 +154,11 @@ def batched_section(torch, mgp, inputs, runs):
                    "seed": 777000 + f, "stream_id": f, "epsilon": 0.01})
     cache = os.path.join(tempfile.gettempdir(), "mgp_batch_tune.txt")
     t0 = time.perf_counter()
-    plan = mgp.BatchPlan(fl, "megopolis", d=4, tune_cache=cache)
+    if shape:
+        bt, ppt, sched = shape
+        plan = mgp.BatchPlan(fl, "megopolis", d=4, block_threads=bt, particles_per_thread=ppt, schedule=sched)
+    else:
+        plan = mgp.BatchPlan(fl, "megopolis", d=4, tune_cache=cache)
     plan_s = time.perf_counter() - t0
     info = plan.info()
     stream = torch.cuda.current_stream()
@@ -585,7 +592,8 @@ def main():
 
     if not args.no_batched:
         log("[bench] batched: 512 filters")
-        result["batched"] = batched_section(torch, mgp, inputs, args.batch_runs)
+        shape = tuple(int(v) for v in args.batch_shape.split(",")) if args.batch_shape else None
+        result["batched"] = batched_section(torch, mgp, inputs, args.batch_runs, shape)
         bt = result["batched"]
         log(f"[bench] batched: graph {bt['graph_ms']:.3f} ms/run, separate {bt['separate_ms']:.3f} ms/run "
             f"-> {bt['speedup_vs_separate']:.2f}x, shape {bt['tuned_shape']}")
