@@ -129,11 +129,25 @@ def cpu_baseline(w_np, variant, eps, stride):
     idx = np.arange(0, n, stride, dtype=np.int32)
     t0 = time.perf_counter()
     B, _, _ = oracle.B_from_weights(w_np, eps)
-    oracle.resample_subset(w_np, variant, B, 12345, idx)
+    ref = oracle.resample_subset(w_np, variant, B, 12345, idx)
     dt = time.perf_counter() - t0
-    return {"value": idx.size / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"single-threaded C oracle: fp64 reduction + B over all {n} weights, then the B-step chains "
-                      f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s"}
+    out = {"value": idx.size / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+           "sample": f"single-threaded C oracle: fp64 reduction + B over all {n} weights, then the B-step chains "
+                     f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s"}
+    # the same sample with the chains split over the host's cores (the
+    # oracle's calls release the GIL and share no state): identical output
+    from concurrent.futures import ThreadPoolExecutor
+    threads = min(16, len(os.sched_getaffinity(0)))
+    if threads > 1:
+        parts = np.array_split(idx, threads)
+        t0 = time.perf_counter()
+        B2, _, _ = oracle.B_from_weights(w_np, eps)
+        with ThreadPoolExecutor(threads) as ex:
+            got = list(ex.map(lambda part: oracle.resample_subset(w_np, variant, B2, 12345, part), parts))
+        dt2 = time.perf_counter() - t0
+        if B2 == B and np.array_equal(np.concatenate(got), ref):
+            out["all_cores"] = {"value": idx.size / dt2, "cores": threads, "seconds": dt2}
+    return out
 
 
 def batched_section(torch, mgp, inputs, runs, shape=None):
