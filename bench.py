@@ -264,6 +264,61 @@ def sweep_section(torch, mgp, inputs):
             "partition_sizes_y4_ms": parts}
 
 
+def configs_section(torch, mgp, inputs):
+    """The two smaller workloads, timed like the paper's experiment (median of
+    the runs after one warm-up, HIP events on the launch stream):
+      - one filter, N = 4096, y = 2, eps = 0.01: Metropolis and Megopolis,
+        resample only (reduction + B + accept loop);
+      - one filter, N = 2^20, y = 0..4, eps = 0.01: the four variants (C1/C2
+        with 128-byte partitions), resample alone and resample + gather of D = 4
+        fp32 states."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def med(fn, runs):
+        times = []
+        for k in range(runs + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn(k)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if k:
+                times.append(a.elapsed_time(b))
+        return float(np.median(times))
+
+    small = {}
+    n = 4096
+    r = mgp.Resampler(n)
+    anc = torch.empty(n, dtype=torch.int32, device=dev)
+    w = torch.from_numpy(inputs.gaussian_weights(n, 2.0, 0)).to(dev)
+    for v in ("metropolis", "megopolis"):
+        ms = med(lambda k: r.resample(w, v, epsilon=0.01, seed=k, out=anc), 20)
+        small[v] = {"ms": ms, "B": r.last_stats()["B"]}
+    mid = {}
+    n = 1 << 20
+    r = mgp.Resampler(n)
+    anc = torch.empty(n, dtype=torch.int32, device=dev)
+    out = torch.empty((n, 4), device=dev)
+    for y in range(5):
+        wn, st = inputs.gaussian_weights_and_states(n, float(y), 4, 0)
+        w, states = torch.from_numpy(wn).to(dev), torch.from_numpy(st).to(dev)
+        for v in ("megopolis", "metropolis", "c1", "c2"):
+            ms_r = med(lambda k: r.resample(w, v, epsilon=0.01, seed=k, out=anc), 5)
+            B = r.last_stats()["B"]
+
+            def step(k):
+                r.resample(w, v, epsilon=0.01, seed=k, out=anc)
+                mgp.gather(states, anc, out=out)
+            mid.setdefault(v, {})[f"y{y}"] = {"resample_ms": ms_r, "with_gather_ms": med(step, 5), "B": B}
+    return {"n4096_y2": {"workload": "single filter, N=4096, y=2, eps=0.01; resample = reduction + B + accept loop; "
+                                     "median of 20 runs", "ms": small},
+            "n2pow20": {"workload": "single filter, N=2^20, y=0..4, eps=0.01, C1/C2 at 128-byte partitions; "
+                                    "resample, and resample + gather of D=4 fp32 states; median of 5 runs",
+                        "ms": mid}}
+
+
 def table2():
     """Table 2 of the paper (K40m): {(variant, B): (resample ratio, RMSE)}."""
     with open(os.path.join(ROOT, "tests", "golden", "sir_table2.json")) as f:
@@ -615,6 +670,11 @@ def main():
     if not args.no_sweep:
         log("[bench] per-variant sweep at N=2^22")
         result["paper_sweep"] = sweep_section(torch, mgp, inputs)
+        log("[bench] configurations N=4096 and N=2^20")
+        result["configs"] = configs_section(torch, mgp, inputs)
+        c2 = result["configs"]["n2pow20"]["ms"]
+        log("[bench] N=2^20 resample ms, y=0..4: " + "; ".join(
+            f"{v} " + "/".join(f"{c2[v][f'y{y}']['resample_ms']:.3f}" for y in range(5)) for v in c2))
         log("[bench] N sweep")
         result["n_sweep"] = n_sweep_section(torch, mgp, inputs)
         log("[bench] " + ", ".join(f"{k}: {v['ms']:.3f} ms" for k, v in result["n_sweep"]["rows"].items()))
