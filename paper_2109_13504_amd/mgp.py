@@ -403,6 +403,16 @@ def _require_weights(w) -> None:
         raise ValueError("weights must be a contiguous 1-D fp32 device tensor")
 
 
+def _require_buffer(t, numel: int, dtype, name: str, device=None) -> None:
+    """The kernels write (or read) `numel` elements through a plain pointer:
+    the tensor must be a contiguous device tensor of that dtype holding at
+    least that many, on the expected device."""
+    if (t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() < numel
+            or (device is not None and t.device != device)):
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor of at least {numel} elements"
+                         + (f" on {device}" if device is not None else ""))
+
+
 class Resampler:
     """Holds a device workspace sized for (n_max, b_max) and calls mgp_resample."""
 
@@ -417,11 +427,12 @@ class Resampler:
     def resample(self, w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
                  stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None,
                  segment: int = 32):
-        _require_weights(w)
+        self._check_weights(w)
         torch = _torch()
         n = w.numel()
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=w.device)
+        _require_buffer(out, n, torch.int32, "out (ancestors)", w.device)
         p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_resample(w.data_ptr(), n, p, out.data_ptr(), self.stats.data_ptr(), self.workspace.data_ptr(),
                      self.ws_bytes, current_stream() if stream is None else stream)
@@ -431,10 +442,11 @@ class Resampler:
                    stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None,
                  segment: int = 32):
         """m ancestors from the n = w.numel() weighted inputs (M != N)."""
-        _require_weights(w)
+        self._check_weights(w)
         torch = _torch()
         if out is None:
             out = torch.empty(int(m), dtype=torch.int32, device=w.device)
+        _require_buffer(out, int(m), torch.int32, "out (ancestors)", w.device)
         p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_resample_m(w.data_ptr(), w.numel(), int(m), p, out.data_ptr(), self.stats.data_ptr(),
                        self.workspace.data_ptr(), self.ws_bytes, current_stream() if stream is None else stream)
@@ -444,7 +456,7 @@ class Resampler:
                   stream_id: int = 0, partition_bytes: int = 128, stream: int | None = None,
                   segment: int = 32) -> None:
         """Reduction, B and offsets only (asynchronous; read last_stats() after a sync)."""
-        _require_weights(w)
+        self._check_weights(w)
         p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_compute_B(w.data_ptr(), w.numel(), p, self.stats.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
                       current_stream() if stream is None else stream)
@@ -453,11 +465,12 @@ class Resampler:
                           stream_id: int = 0, partition_bytes: int = 128, out=None, stream: int | None = None,
                  segment: int = 32):
         """The accept loop only, after compute_B with the same arguments."""
-        _require_weights(w)
+        self._check_weights(w)
         torch = _torch()
         n = w.numel()
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=w.device)
+        _require_buffer(out, n, torch.int32, "out (ancestors)", w.device)
         p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
         mgp_resample_prepared(w.data_ptr(), n, p, out.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
                               current_stream() if stream is None else stream)
@@ -465,6 +478,11 @@ class Resampler:
 
     def last_stats(self) -> dict:
         return decode_stats(self.stats)
+
+    def _check_weights(self, w) -> None:
+        _require_weights(w)
+        if w.device != self.workspace.device:
+            raise ValueError(f"weights are on {w.device}, the workspace on {self.workspace.device}")
 
 
 def resample(w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
@@ -485,8 +503,11 @@ def gather(states, anc, out=None, stream: int | None = None):
     st2 = states.view(states.shape[0], -1)
     n_states, d = st2.shape
     n_out = anc.numel()
+    if anc.device != states.device:
+        raise ValueError("ancestors and states must be on the same device")
     if out is None:
         out = torch.empty((n_out, d), dtype=torch.float32, device=states.device)
+    _require_buffer(out, n_out * d, torch.float32, "out (gathered states)", states.device)
     mgp_gather(st2.data_ptr(), n_states, d, anc.data_ptr(), n_out, out.data_ptr(),
                current_stream() if stream is None else stream)
     return out
@@ -502,10 +523,20 @@ class BatchPlan:
     def __init__(self, filters, variant="megopolis", d: int = 0, partition_bytes: int = 128, b_max: int = 0,
                  block_threads: int = 0, particles_per_thread: int = 0, schedule: int = 0, use_graph: bool = True,
                  tune_cache: str | None = None, stream: int | None = None):
+        torch = _torch()
         self.filters = filters
         descs = []
-        for f in filters:
+        for k, f in enumerate(filters):
             st = f.get("states")
+            _require_weights(f["w"])
+            n = f["w"].numel()
+            dev = f["w"].device
+            _require_buffer(f["anc"], n, torch.int32, f"filter {k}: anc", dev)
+            if st is not None:
+                _require_buffer(st, n * max(int(d), 1), torch.float32, f"filter {k}: states", dev)
+                _require_buffer(f["out"], n * max(int(d), 1), torch.float32, f"filter {k}: out", dev)
+            if f.get("stats") is not None:
+                _require_buffer(f["stats"], STATS_BYTES, torch.uint8, f"filter {k}: stats", dev)
             descs.append(mgp_filter_desc(f["w"].data_ptr(), f["w"].numel(), int(f.get("B", 0)),
                                          float(f.get("epsilon", 0.01)), int(f.get("seed", 0)) & (2**64 - 1),
                                          int(f.get("stream_id", 0)), 0, f["anc"].data_ptr(),
@@ -560,6 +591,13 @@ class Server:
 
     def submit(self, w, n: int | None = None, B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,
                states=None) -> int:
+        if not isinstance(w, int):
+            _require_weights(w)
+            if n is not None and int(n) > w.numel():
+                raise ValueError(f"n = {n} exceeds the {w.numel()} weights given")
+        if states is not None and not isinstance(states, int):
+            nn = n if n is not None else w.numel()
+            _require_buffer(states, int(nn) * max(int(self.d), 1), _torch().float32, "states")
         wp = w if isinstance(w, int) else w.data_ptr()
         n = n if n is not None else w.numel()
         sp = None if states is None else (states if isinstance(states, int) else states.data_ptr())

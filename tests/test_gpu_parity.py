@@ -222,6 +222,34 @@ def test_argument_errors(torch_dev, mgp):
     assert e.value.code == mgp.MGP_ERANGE
 
 
+def test_binding_rejects_undersized_or_mistyped_buffers(torch_dev, mgp):
+    """The kernels write through plain pointers, so the binding checks every
+    caller-supplied buffer before anything is enqueued."""
+    torch, dev = torch_dev
+    w = torch.ones(64, device=dev)
+    r = mgp.Resampler(64)
+    sentinel = torch.full((64,), 7, dtype=torch.int32, device=dev)
+    for bad in (torch.empty(63, dtype=torch.int32, device=dev), torch.empty(64, dtype=torch.int64, device=dev),
+                torch.empty(128, dtype=torch.int32, device=dev)[::2], torch.empty(64, dtype=torch.int32)):
+        with pytest.raises(ValueError):
+            r.resample(w, "megopolis", B=3, out=bad)
+        with pytest.raises(ValueError):
+            r.resample_prepared(w, "megopolis", B=3, out=bad)
+    with pytest.raises(ValueError):
+        r.resample_m(w, 65, "megopolis", B=3, out=sentinel)
+    states = torch.zeros((64, 4), device=dev)
+    anc = torch.zeros(64, dtype=torch.int32, device=dev)
+    with pytest.raises(ValueError):
+        mgp.gather(states, anc, out=torch.empty((63, 4), device=dev))
+    with pytest.raises(ValueError):
+        mgp.BatchPlan([{"w": w, "anc": torch.empty(32, dtype=torch.int32, device=dev), "B": 3}], "megopolis")
+    with pytest.raises(ValueError):
+        mgp.BatchPlan([{"w": w, "anc": anc, "B": 3, "states": states, "out": torch.empty((64, 2), device=dev)}],
+                      "megopolis", d=4)
+    torch.cuda.synchronize()
+    assert (sentinel == 7).all()
+
+
 def test_b_clamp_and_explicit_B(torch_dev, mgp):
     torch, dev = torch_dev
     n = 4096
