@@ -414,13 +414,14 @@ K40M_MEGOPOLIS_Y4 = {1 << 15: 5.170e-4, 1 << 16: 8.173e-4, 1 << 17: 0.0014, 1 <<
 
 def n_sweep_section(torch, mgp, inputs):
     """Megopolis resample time (reduction, B, offsets, accept loop; no
-    gather) against N = 2^15 .. 2^26, Gaussian-likelihood weights y = 4,
-    eps = 0.01, median of 5; the paper's Table 3 y = 4 column as context."""
+    gather) against N = 2^12 .. 2^26, Gaussian-likelihood weights y = 4,
+    eps = 0.01, median of 5; the paper's Table 3 y = 4 column (from 2^15) as
+    context."""
     import numpy as np
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     rows = {}
-    for ln in range(15, 27):
+    for ln in range(12, 27):
         n = 1 << ln
         w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
         anc = torch.empty(n, dtype=torch.int32, device=dev)

@@ -878,9 +878,7 @@ int mgp_batch_run_separate(mgp_batch_plan* p, void* stream)
         const mgp_filter_desc& x = p->filters[f];
         Params q{p->variant, x.B, x.epsilon, x.seed, x.stream_id, p->partition_bytes, p->b_max};
         char* ws = p->d_sep + p->sep_off[f];
-        int rc = enqueue_reduce_finalize(x.w_dev, (uint32_t)x.n, q, p->variant == kMegopolis, ws, x.stats_dev, s);
-        if (rc) return rc;
-        rc = enqueue_loop(x.w_dev, (uint32_t)x.n, q, ws, x.ancestors_dev, s);
+        int rc = enqueue_resample(x.w_dev, (uint32_t)x.n, q, ws, x.stats_dev, x.ancestors_dev, s);
         if (rc) return rc;
         if (x.states_dev) {
             rc = enqueue_gather(x.states_dev, (uint32_t)x.n, p->d, x.ancestors_dev, (uint32_t)x.n, x.out_states_dev, s);

@@ -161,6 +161,177 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
     if (i < m) anc[i] = (int32_t)k;
 }
 
+// Megopolis for a small filter in one launch (mgp_resample, n <= kSmallMaxN).
+// Every block copies the weights into LDS as the mirror M[k] = w[k mod n],
+// repeats the reduction of k_reduce and k_finalize chunk by chunk in the
+// same order (so the fp64 sum, B and the stats are bit-identical to the
+// three-launch path), draws the offsets into LDS kSmallOffsets at a time,
+// and runs the chains of its own particles against the LDS mirror, twenty
+// steps' loads per round as in k_megopolis_mirror_deep. For small n the
+// three-launch path is two kernel gaps, a finalize and B/20 round trips to
+// L2; here it is one launch and LDS round trips.
+constexpr uint32_t kSmallMaxN = 8192;
+constexpr uint32_t kSmallPad = 512;       // lanes past n: slot <= n + 255 + n - 1 + 63 < 2n + 512
+constexpr uint32_t kSmallOffsets = 4000;  // a multiple of 4 (offset calls), 5 (u blocks) and 20 (rounds)
+constexpr uint32_t kSmallMaxParts = kSmallMaxN / kReduceChunk;
+static_assert(kSmallMaxN % kReduceChunk == 0 && kSmallMaxN <= (uint64_t)kReduceChunk * kMaxPartials,
+              "the reduction of a small filter has at most kSmallMaxParts chunks");
+static_assert(kSmallOffsets % 20 == 0, "offset passes must start on a round boundary");
+
+__global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* __restrict__ w, uint32_t n,
+                                                                  uint32_t nparts, uint32_t chunk, uint32_t vec,
+                                                                  FinalizeArgs a, mgp_stats* __restrict__ st_ws,
+                                                                  mgp_stats* __restrict__ st_user, uint32_t seg_mask,
+                                                                  int32_t* __restrict__ anc)
+{
+    __shared__ __align__(16) float M[2 * kSmallMaxN + kSmallPad];
+    __shared__ uint32_t offs[kSmallOffsets];
+    __shared__ Partial parts[kSmallMaxParts];
+    __shared__ mgp_stats st_local;
+    // 1. the mirror: every load of a thread is issued before its first LDS
+    //    store (clamped indices, no branch around a load), so the copy costs
+    //    one round trip to L2, not one per element
+    if (vec) {  // w 16-byte aligned and n % 4 == 0
+        constexpr uint32_t kIt = kSmallMaxN / (4u * kLoopThreads);
+        const float4* w4 = reinterpret_cast<const float4*>(w);
+        const uint32_t last4 = n / 4u - 1u;
+        float4 v[kIt];
+#pragma unroll
+        for (uint32_t it = 0; it < kIt; ++it) {
+            const uint32_t k4 = threadIdx.x + it * kLoopThreads;
+            v[it] = w4[k4 < last4 ? k4 : last4];
+        }
+        // lanes past the end store the last element again, to its own place
+#pragma unroll
+        for (uint32_t it = 0; it < kIt; ++it) {
+            const uint32_t k4 = threadIdx.x + it * kLoopThreads;
+            const uint32_t c4 = k4 < last4 ? k4 : last4;
+            *reinterpret_cast<float4*>(M + 4u * c4) = v[it];
+            *reinterpret_cast<float4*>(M + 4u * c4 + n) = v[it];
+        }
+    } else {
+        constexpr uint32_t kIt = kSmallMaxN / kLoopThreads;
+        float v[kIt];
+#pragma unroll
+        for (uint32_t it = 0; it < kIt; ++it) {
+            const uint32_t k = threadIdx.x + it * kLoopThreads;
+            v[it] = w[k < n ? k : n - 1u];
+        }
+#pragma unroll
+        for (uint32_t it = 0; it < kIt; ++it) {
+            const uint32_t k = threadIdx.x + it * kLoopThreads;
+            const uint32_t c = k < n ? k : n - 1u;
+            M[c] = v[it];
+            M[c + n] = v[it];
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < kSmallPad; k += kLoopThreads) M[2u * n + k] = M[k % n];
+    __syncthreads();
+    // 2. the reduction, one chunk at a time with k_reduce's thread mapping
+    for (uint32_t p = 0; p < nparts; ++p) {
+        const uint64_t start = (uint64_t)p * chunk;
+        const uint64_t stop = start + chunk < (uint64_t)n ? start + chunk : (uint64_t)n;
+        const uint64_t end = stop > start ? stop : start;
+        float mx = 0.0f;
+        double s = 0.0;
+        uint32_t bad = 0;
+        if (vec)
+            reduce_range<true>(M, n, start, end, nullptr, mx, s, bad);
+        else
+            reduce_range<false>(M, n, start, end, nullptr, mx, s, bad);
+        block_reduce(mx, s, bad);
+        if (threadIdx.x == 0) parts[p] = Partial{s, mx, bad};
+        __syncthreads();
+    }
+    // 3. B and the stats; block 0 returns them. The workspace record is
+    //    marked unusable for mgp_resample_prepared (n = 0): this path leaves
+    //    no offsets or mirror there.
+    const uint32_t B = finalize_one(parts, nparts, a, &st_local, blockIdx.x == 0 ? st_user : nullptr, nullptr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        mgp_stats r = st_local;
+        r.n = 0;
+        r.tag = 0;
+        *st_ws = r;
+    }
+    const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
+    if (B == 0) {  // invalid weights
+        if (i < n) anc[i] = -1;
+        return;
+    }
+    // 4. the chains; lanes past n run too, in bounds thanks to the padding
+    const uint32_t ia4 = (i & ~seg_mask) * 4u;
+    const uint32_t il4 = (i & seg_mask) * 4u;
+    const char* Mb = reinterpret_cast<const char*>(M);
+    uint32_t kk = i * 4u;
+    float wk = M[i];
+    for (uint32_t base = 0; base < B; base += kSmallOffsets) {
+        const uint32_t cnt = B - base < kSmallOffsets ? B - base : kSmallOffsets;
+        __syncthreads();  // every lane is done with the previous pass's offsets
+        for (uint32_t c = threadIdx.x; c < (cnt + 3u) / 4u; c += kLoopThreads) {
+            const Words x = philox(base / 4u + c, kTagOffset, a.stream_id, 0u, a.key0, a.key1);
+            const uint32_t o[4] = {x.x0, x.x1, x.x2, x.x3};
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                if (4u * c + r < cnt) offs[4u * c + r] = uniform_index(o[r], n);
+        }
+        __syncthreads();
+        uint32_t s0 = 0;
+        for (; s0 + 20u <= cnt; s0 += 20u) {
+            float wj[20];
+            uint32_t jb[20];
+#pragma unroll
+            for (uint32_t s = 0; s < 20u; ++s) {
+                const uint32_t o = offs[s0 + s];
+                const uint32_t oa4 = (o & ~seg_mask) * 4u;
+                const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
+                wj[s] = *reinterpret_cast<const float*>(Mb + oa4 + voff);
+                jb[s] = voff + oa4;
+            }
+#pragma unroll
+            for (uint32_t g = 0; g < 4u; ++g) {
+                const UBlock ub = u_block(philox((base + s0) / 5u + g, kTagU, a.stream_id, i, a.key0, a.key1));
+#pragma unroll
+                for (uint32_t s = 0; s < 5u; ++s) {
+                    const float prod = ub.u[s] * wk;
+                    const bool acc = prod <= wj[g * 5u + s];
+                    kk = acc ? jb[g * 5u + s] : kk;
+                    wk = acc ? wj[g * 5u + s] : wk;
+                }
+            }
+        }
+        for (; s0 < cnt; s0 += 5u) {
+            const uint32_t m5 = cnt - s0 < 5u ? cnt - s0 : 5u;
+            float wj[5];
+            uint32_t jb[5];
+#pragma unroll
+            for (uint32_t s = 0; s < 5u; ++s) {
+                if (s < m5) {
+                    const uint32_t o = offs[s0 + s];
+                    const uint32_t oa4 = (o & ~seg_mask) * 4u;
+                    const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
+                    wj[s] = *reinterpret_cast<const float*>(Mb + oa4 + voff);
+                    jb[s] = voff + oa4;
+                }
+            }
+            const UBlock ub = u_block(philox((base + s0) / 5u, kTagU, a.stream_id, i, a.key0, a.key1));
+#pragma unroll
+            for (uint32_t s = 0; s < 5u; ++s) {
+                if (s < m5) {
+                    const float prod = ub.u[s] * wk;
+                    const bool acc = prod <= wj[s];
+                    kk = acc ? jb[s] : kk;
+                    wk = acc ? wj[s] : wk;
+                }
+            }
+        }
+    }
+    if (i < n) {
+        const uint32_t k = kk / 4u;
+        anc[i] = (int32_t)(k >= n ? k - n : k);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 4. Gather: out[i] = states[anc[i]] (rows of d fp32). With d % 4 == 0 and
 //    16-byte aligned rows every thread copies one float4; otherwise one
@@ -360,6 +531,41 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
     return check_launch("resample kernel");
 }
 
+// mgp_resample for Megopolis with n <= kSmallMaxN: one launch of
+// k_megopolis_small. Its reduction uses the chunks and thread mapping that
+// enqueue_reduce_finalize uses for the same n and weight alignment.
+int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
+                  hipStream_t stream)
+{
+    const uint32_t g = reduce_blocks(n);
+    const uint32_t chunk = reduce_chunk(n, g);
+    const uint32_t vec = ((((uintptr_t)w & 15u) == 0) && n % 4u == 0) ? 1u : 0u;
+    FinalizeArgs a;
+    a.n = n;
+    a.eps = p.eps;
+    a.B_user = p.B;
+    a.b_max = p.b_max;
+    a.make_offsets = 0u;
+    a.key0 = (uint32_t)p.seed;
+    a.key1 = (uint32_t)(p.seed >> 32);
+    a.stream_id = p.stream_id;
+    a.tag = call_tag(n, p.variant, p.seed, p.stream_id);
+    mgp_stats* st_ws = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
+    const dim3 grid((n + kLoopThreads - 1u) / kLoopThreads);
+    hipLaunchKernelGGL(k_megopolis_small, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, vec, a, st_ws, st_user,
+                       p.segment - 1u, anc);
+    return check_launch("megopolis kernel (one launch)");
+}
+
+int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
+                     hipStream_t stream)
+{
+    if (p.variant == kMegopolis && n <= kSmallMaxN) return enqueue_small(w, n, p, ws, st_user, anc, stream);
+    int rc = enqueue_reduce_finalize(w, n, p, p.variant == kMegopolis, ws, st_user, stream);
+    if (rc) return rc;
+    return enqueue_loop(w, n, p, ws, anc, stream);
+}
+
 // One element (or float4) per thread up to 2^20 blocks, grid-stride beyond.
 static uint32_t gather_blocks(uint64_t total)
 {
@@ -461,11 +667,8 @@ int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_
     if (rc) return rc;
     rc = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
     if (rc) return rc;
-    char* ws = static_cast<char*>(workspace_dev);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    rc = enqueue_reduce_finalize(w_dev, (uint32_t)n, p, p.variant == kMegopolis, ws, stats_dev, s);
-    if (rc) return rc;
-    return enqueue_loop(w_dev, (uint32_t)n, p, ws, ancestors_dev, s);
+    return enqueue_resample(w_dev, (uint32_t)n, p, static_cast<char*>(workspace_dev), stats_dev, ancestors_dev,
+                            static_cast<hipStream_t>(stream));
 }
 
 int mgp_resample_m(const float* w_dev, int32_t n, int32_t m, const mgp_params* params, int32_t* ancestors_dev,

@@ -104,7 +104,8 @@ __device__ __forceinline__ void mirror_pad(const float* __restrict__ w, uint32_t
 //    offsets are drawn before the particle loop; here in parallel, four per
 //    Philox call).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void finalize_one(const Partial* __restrict__ part, uint32_t nparts, const FinalizeArgs& a,
+// Returns B (0 for invalid weights) in every thread.
+__device__ __forceinline__ uint32_t finalize_one(const Partial* __restrict__ part, uint32_t nparts, const FinalizeArgs& a,
                              mgp_stats* __restrict__ st, mgp_stats* __restrict__ st_user,
                              uint32_t* __restrict__ offsets)
 {
@@ -168,6 +169,7 @@ __device__ __forceinline__ void finalize_one(const Partial* __restrict__ part, u
             }
         }
     }
+    return B;
 }
 
 }  // namespace mgp

@@ -1,0 +1,110 @@
+"""The one-launch Megopolis path of mgp_resample for small filters
+(n <= 8192): bit-exact ancestors against the oracle across sizes, B on both
+sides of the 20-step rounds and of the 4000-offset passes, 32- and 64-wide
+segments; stats bit-identical to the three-launch reduction (mgp_compute_B)
+for aligned and unaligned weights; invalid weights; and the workspace left
+unusable for mgp_resample_prepared."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_13504_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SMALL_MAX = 8192
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2109_13504_amd import mgp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mgp.lib()
+    return torch, torch.device("cuda:0"), mgp
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 100, 4095, 4096, 4101, 6000, SMALL_MAX - 1, SMALL_MAX])
+def test_ancestors_match_oracle(env, n):
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 3.0, 23)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    for B in (1, 4, 19, 20, 21, 354, 4001):
+        if B == 4001 and n > 4101:
+            continue  # the oracle's cost; the pass boundary is covered at the smaller sizes
+        for seg in (32, 64):
+            got = r.resample(wd, "megopolis", B=B, seed=500 + B, stream_id=9, segment=seg).cpu().numpy()
+            ref = oracle.resample_m(w, n, "megopolis", B, 500 + B, stream_id=9, segment=seg)
+            np.testing.assert_array_equal(got, ref, err_msg=f"n={n} B={B} segment={seg}")
+            st = r.last_stats()
+            assert st["B"] == B and st["status"] == 0 and st["n"] == n
+
+
+def test_two_offset_passes_with_epsilon_and_clamp(env):
+    """B from epsilon clamped to b_max = 8003: two full passes of 4000
+    offsets and a tail of 3."""
+    torch, dev, mgp = env
+    n = 2048
+    w = inputs.gaussian_weights(n, 4.0, 3)
+    w[:] = np.float32(1e-30)
+    w[17] = np.float32(1.0)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n, b_max=8003)
+    got = r.resample(wd, "megopolis", epsilon=0.01, seed=3).cpu().numpy()
+    st = r.last_stats()
+    assert st["B"] == 8003 and st["clamped"] == 1
+    np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", 8003, 3))
+
+
+@pytest.mark.parametrize("n,shift", [(4096, 0), (4096, 1), (4101, 0), (SMALL_MAX, 0), (SMALL_MAX - 3, 1)])
+def test_stats_equal_three_launch_reduction(env, n, shift):
+    """The fused kernel repeats k_reduce's chunks and thread mapping (float4
+    or scalar, by the weights' alignment), so every stats field, the fp64 sum
+    included, equals what mgp_compute_B writes for the same weights."""
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 2.0, 31)
+    base = torch.zeros(n + 4, device=dev)
+    wd = base[shift:shift + n]
+    wd.copy_(torch.from_numpy(w))
+    assert (wd.data_ptr() % 16 == 0) == (shift == 0)
+    r = mgp.Resampler(n)
+    r.resample(wd, "megopolis", epsilon=0.01, seed=11, stream_id=4)
+    fused = r.last_stats()
+    r.compute_B(wd, "megopolis", epsilon=0.01, seed=11, stream_id=4)
+    three = r.last_stats()
+    assert fused == three
+    B, _, _ = oracle.B_from_weights(w, 0.01)
+    assert fused["B"] == B
+    s = oracle.reduce(w).w_sum
+    assert abs(fused["w_sum"] - s) <= 1e-12 * s
+
+
+def test_invalid_weights_and_prepared_refused(env):
+    torch, dev, mgp = env
+    n = 1000
+    w = inputs.gaussian_weights(n, 1.0, 2)
+    w[400] = np.nan
+    r = mgp.Resampler(n)
+    got = r.resample(torch.from_numpy(w).to(dev), "megopolis", epsilon=0.01, seed=1).cpu().numpy()
+    assert (got == -1).all() and r.last_stats()["status"] == mgp.MGP_EWEIGHTS
+    # a valid call, then a prepared loop with the same params: the one-launch
+    # path leaves no offsets or mirror in the workspace, so the loop refuses
+    w = inputs.gaussian_weights(n, 1.0, 2)
+    wd = torch.from_numpy(w).to(dev)
+    r.resample(wd, "megopolis", B=7, seed=1)
+    assert (r.resample_prepared(wd, "megopolis", B=7, seed=1).cpu().numpy() == -1).all()
+
+
+def test_first_size_past_the_limit_uses_three_launches(env):
+    torch, dev, mgp = env
+    n = SMALL_MAX + 1
+    w = inputs.gaussian_weights(n, 3.0, 5)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    got = r.resample(wd, "megopolis", B=41, seed=2).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", 41, 2))
+    # and the prepared loop works after it, as before
+    r.compute_B(wd, "megopolis", B=41, seed=2)
+    np.testing.assert_array_equal(r.resample_prepared(wd, "megopolis", B=41, seed=2).cpu().numpy(), got)
