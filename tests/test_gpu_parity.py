@@ -5,7 +5,7 @@ Sizes: the small single-filter workload (N = 4096, y = 2), ragged sizes that
 exercise partial waves, the unrolled-loop tails and the C1/C2 tail partition,
 the N = 2^20 sweep over y = 0..4 for all four variants, and N = 2^24 at
 y = 4 in the launch configuration the benchmark times (sampled particles,
-whose chains the oracle recomputes one by one)."""
+whose chains the oracle recomputes one by one, and once the full array)."""
 import numpy as np
 import pytest
 
@@ -141,6 +141,33 @@ def test_n2pow24_sampled(torch_dev, mgp):
         assert anc.min() >= 0 and anc.max() < n
         np.testing.assert_array_equal(out.cpu().numpy()[sample], st[anc[sample]])
         del out
+
+
+def test_n2pow24_full_array_megopolis(torch_dev, mgp):
+    """Every ancestor and every gathered row at N = 2^24, y = 4, D = 8, in the
+    benchmark's launch sequence (mgp_compute_B, mgp_resample_prepared,
+    mgp_gather). The oracle's chains are split over the host's cores (its
+    calls share no state), about 6 x 10^9 chain steps in all."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    torch, dev = torch_dev
+    n, d = 1 << 24, 8
+    w, st = inputs.gaussian_weights_and_states(n, 4.0, d, 0)
+    wd, sd = _to_dev(torch, dev, w), _to_dev(torch, dev, st)
+    r = mgp.Resampler(n)
+    r.compute_B(wd, "megopolis", epsilon=0.01, seed=99)
+    anc_d = r.resample_prepared(wd, "megopolis", epsilon=0.01, seed=99)
+    out = mgp.gather(sd, anc_d).cpu().numpy()
+    anc = anc_d.cpu().numpy()
+    stats = r.last_stats()
+    _check_stats(stats, w)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts = np.array_split(np.arange(n, dtype=np.int32), 4 * threads)
+    with ThreadPoolExecutor(threads) as ex:
+        ref = np.concatenate(list(ex.map(lambda idx: oracle.resample_subset(w, "megopolis", stats["B"], 99, idx),
+                                         parts)))
+    np.testing.assert_array_equal(anc, ref)
+    np.testing.assert_array_equal(out, st[anc])
 
 
 def test_megopolis_uniform_weights_permutation_at_scale(torch_dev, mgp):
