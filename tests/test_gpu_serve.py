@@ -73,7 +73,7 @@ def run_mixed(srv, reqs):
     return out
 
 
-@pytest.mark.parametrize("variant", ["megopolis", "metropolis"])
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2"])
 def test_alone_equals_mixed_equals_oracle(env, variant):
     torch, dev, mgp = env
     d = 16
@@ -90,7 +90,7 @@ def test_alone_equals_mixed_equals_oracle(env, variant):
             np.testing.assert_array_equal(alone[k][2], mixed[k][2])
         else:
             assert mixed[k][2] is None
-    for k in (0, 5, 11):
+    for k in range(len(reqs)):
         r = reqs[k]
         ref = oracle.resample(r["w_np"], variant, alone[k][0], r["seed"], stream_id=r["stream_id"])
         np.testing.assert_array_equal(alone[k][1], ref)
