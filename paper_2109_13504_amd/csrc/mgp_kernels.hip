@@ -161,7 +161,8 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
     if (i < m) anc[i] = (int32_t)k;
 }
 
-// Megopolis for a small filter in one launch (mgp_resample, n <= kSmallMaxN).
+// Megopolis (Algorithm 5, B by eq. (proposition) of Section 4.1) for a small
+// filter in one launch (mgp_resample, n <= kSmallMaxN).
 // Every block copies the weights into LDS as the mirror M[k] = w[k mod n],
 // repeats the reduction of k_reduce and k_finalize chunk by chunk in the
 // same order (so the fp64 sum, B and the stats are bit-identical to the
