@@ -90,10 +90,10 @@ int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes);
  *      (proposition) (Section 4.1), clamped to [1, b_max]; Megopolis offsets
  *      o_0..o_{B-1} (Algorithm 5) are generated here;
  *   3. the accept loop: ancestors_dev[i] = k_i for i in [0, n).
- * For MGP_MEGOPOLIS with n <= 8192 the three steps run as one launch that
- * keeps the weights in LDS (same results, stats included); it leaves no
- * offsets in the workspace, so only mgp_compute_B prepares a
- * mgp_resample_prepared call.
+ * For n <= 8192 (MGP_MEGOPOLIS) or n <= 4096 (the other variants) the three
+ * steps run as one launch that keeps the weights in LDS (same results, stats
+ * included); it leaves nothing in the workspace for a following
+ * mgp_resample_prepared, which only mgp_compute_B prepares.
  * w_dev          : n fp32 weights, device, contiguous, >= 0 and finite.
  * ancestors_dev  : n int32, device, written.
  * stats_dev      : device mgp_stats written by step 2, or NULL.

@@ -172,6 +172,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
 // three-launch path is two kernel gaps, a finalize and B/20 round trips to
 // L2; here it is one launch and LDS round trips.
 constexpr uint32_t kSmallMaxN = 8192;
+constexpr uint32_t kSmallMaxNOther = 4096;  // Metropolis, C1, C2: chains without shared indices gain less
 constexpr uint32_t kSmallPad = 512;       // lanes past n: slot <= n + 255 + n - 1 + 63 < 2n + 512
 constexpr uint32_t kSmallOffsets = 4000;  // a multiple of 4 (offset calls), 5 (u blocks) and 20 (rounds)
 constexpr uint32_t kSmallMaxParts = kSmallMaxN / kReduceChunk;
@@ -179,20 +180,21 @@ static_assert(kSmallMaxN % kReduceChunk == 0 && kSmallMaxN <= (uint64_t)kReduceC
               "the reduction of a small filter has at most kSmallMaxParts chunks");
 static_assert(kSmallOffsets % 20 == 0, "offset passes must start on a round boundary");
 
-__global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* __restrict__ w, uint32_t n,
-                                                                  uint32_t nparts, uint32_t chunk, uint32_t vec,
-                                                                  FinalizeArgs a, mgp_stats* __restrict__ st_ws,
-                                                                  mgp_stats* __restrict__ st_user, uint32_t seg_mask,
-                                                                  int32_t* __restrict__ anc)
+// The first steps of the one-launch kernels: the LDS mirror
+// M[k] = w[k mod n], k < 2n + kSmallPad, then the reduction and B exactly as
+// k_reduce and k_finalize compute them (chunks of `chunk` weights with
+// k_reduce's thread mapping: float4 folds when fold_vec). Block 0 returns the
+// stats. Returns B (0 for invalid weights) in every thread.
+__device__ __forceinline__ uint32_t small_prologue(const float* __restrict__ w, uint32_t n, uint32_t nparts,
+                                                   uint32_t chunk, uint32_t copy_vec, uint32_t fold_vec,
+                                                   const FinalizeArgs& a, mgp_stats* __restrict__ st_ws,
+                                                   mgp_stats* __restrict__ st_user, float* __restrict__ M,
+                                                   Partial* __restrict__ parts, mgp_stats* __restrict__ st_local)
 {
-    __shared__ __align__(16) float M[2 * kSmallMaxN + kSmallPad];
-    __shared__ uint32_t offs[kSmallOffsets];
-    __shared__ Partial parts[kSmallMaxParts];
-    __shared__ mgp_stats st_local;
     // 1. the mirror: every load of a thread is issued before its first LDS
     //    store (clamped indices, no branch around a load), so the copy costs
     //    one round trip to L2, not one per element
-    if (vec) {  // w 16-byte aligned and n % 4 == 0
+    if (copy_vec) {  // w 16-byte aligned and n % 4 == 0
         constexpr uint32_t kIt = kSmallMaxN / (4u * kLoopThreads);
         const float4* w4 = reinterpret_cast<const float4*>(w);
         const uint32_t last4 = n / 4u - 1u;
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* _
         float mx = 0.0f;
         double s = 0.0;
         uint32_t bad = 0;
-        if (vec)
+        if (fold_vec)
             reduce_range<true>(M, n, start, end, nullptr, mx, s, bad);
         else
             reduce_range<false>(M, n, start, end, nullptr, mx, s, bad);
@@ -248,13 +250,27 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* _
     // 3. B and the stats; block 0 returns them. The workspace record is
     //    marked unusable for mgp_resample_prepared (n = 0): this path leaves
     //    no offsets or mirror there.
-    const uint32_t B = finalize_one(parts, nparts, a, &st_local, blockIdx.x == 0 ? st_user : nullptr, nullptr);
+    const uint32_t B = finalize_one(parts, nparts, a, st_local, blockIdx.x == 0 ? st_user : nullptr, nullptr);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        mgp_stats r = st_local;
+        mgp_stats r = *st_local;
         r.n = 0;
         r.tag = 0;
         *st_ws = r;
     }
+    return B;
+}
+
+__global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* __restrict__ w, uint32_t n,
+                                                                  uint32_t nparts, uint32_t chunk, uint32_t vec,
+                                                                  FinalizeArgs a, mgp_stats* __restrict__ st_ws,
+                                                                  mgp_stats* __restrict__ st_user, uint32_t seg_mask,
+                                                                  int32_t* __restrict__ anc)
+{
+    __shared__ __align__(16) float M[2 * kSmallMaxN + kSmallPad];
+    __shared__ uint32_t offs[kSmallOffsets];
+    __shared__ Partial parts[kSmallMaxParts];
+    __shared__ mgp_stats st_local;
+    const uint32_t B = small_prologue(w, n, nparts, chunk, vec, vec, a, st_ws, st_user, M, parts, &st_local);
     const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
     if (B == 0) {  // invalid weights
         if (i < n) anc[i] = -1;
@@ -331,6 +347,31 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* _
         const uint32_t k = kk / 4u;
         anc[i] = (int32_t)(k >= n ? k - n : k);
     }
+}
+
+// Metropolis, C1 and C2 (Algorithms 2-4) for a small filter in one launch:
+// the same prologue, then each thread runs its particle's chain of k_resample
+// against the weights in LDS.
+template <int V>
+__global__ __launch_bounds__(kLoopThreads) void k_resample_small(const float* __restrict__ w, uint32_t n,
+                                                                 uint32_t nparts, uint32_t chunk, uint32_t copy_vec,
+                                                                 uint32_t fold_vec, FinalizeArgs a,
+                                                                 mgp_stats* __restrict__ st_ws,
+                                                                 mgp_stats* __restrict__ st_user, uint32_t n_w,
+                                                                 uint32_t n_part, int32_t* __restrict__ anc)
+{
+    __shared__ __align__(16) float M[2 * kSmallMaxN + kSmallPad];
+    __shared__ Partial parts[kSmallMaxParts];
+    __shared__ mgp_stats st_local;
+    const uint32_t B = small_prologue(w, n, nparts, chunk, copy_vec, fold_vec, a, st_ws, st_user, M, parts, &st_local);
+    const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
+    if (i >= n) return;
+    if (B == 0) {  // invalid weights
+        anc[i] = -1;
+        return;
+    }
+    const LoopParams P{M, nullptr, n, B, a.key0, a.key1, a.stream_id, n_w, n_part};
+    anc[i] = (int32_t)run_chain<V, true>(P, i, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,15 +573,18 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
     return check_launch("resample kernel");
 }
 
-// mgp_resample for Megopolis with n <= kSmallMaxN: one launch of
-// k_megopolis_small. Its reduction uses the chunks and thread mapping that
-// enqueue_reduce_finalize uses for the same n and weight alignment.
+// mgp_resample with n <= kSmallMaxN (Megopolis) or kSmallMaxNOther: one
+// launch of k_megopolis_small or k_resample_small. The reduction uses the chunks, thread mapping and fold
+// width that enqueue_reduce_finalize uses for the same n, variant and weight
+// alignment (float4 folds need a 16-byte aligned w, and with a mirror n % 4 == 0).
 int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
                   hipStream_t stream)
 {
     const uint32_t g = reduce_blocks(n);
     const uint32_t chunk = reduce_chunk(n, g);
-    const uint32_t vec = ((((uintptr_t)w & 15u) == 0) && n % 4u == 0) ? 1u : 0u;
+    const bool aligned = ((uintptr_t)w & 15u) == 0;
+    const uint32_t copy_vec = (aligned && n % 4u == 0) ? 1u : 0u;
+    const uint32_t fold_vec = p.variant == kMegopolis ? copy_vec : (aligned ? 1u : 0u);
     FinalizeArgs a;
     a.n = n;
     a.eps = p.eps;
@@ -553,15 +597,34 @@ int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_sta
     a.tag = call_tag(n, p.variant, p.seed, p.stream_id);
     mgp_stats* st_ws = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
     const dim3 grid((n + kLoopThreads - 1u) / kLoopThreads);
-    hipLaunchKernelGGL(k_megopolis_small, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, vec, a, st_ws, st_user,
-                       p.segment - 1u, anc);
-    return check_launch("megopolis kernel (one launch)");
+    const uint32_t n_w = p.partition_bytes / 4u;
+    const uint32_t n_part = (uint32_t)(((uint64_t)n + n_w - 1u) / n_w);
+    switch (p.variant) {
+    case kMegopolis:
+        hipLaunchKernelGGL(k_megopolis_small, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, copy_vec, a,
+                           st_ws, st_user, p.segment - 1u, anc);
+        break;
+    case kMetropolis:
+        hipLaunchKernelGGL(k_resample_small<kMetropolis>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk,
+                           copy_vec, fold_vec, a, st_ws, st_user, n_w, n_part, anc);
+        break;
+    case kC1:
+        hipLaunchKernelGGL(k_resample_small<kC1>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, copy_vec,
+                           fold_vec, a, st_ws, st_user, n_w, n_part, anc);
+        break;
+    default:
+        hipLaunchKernelGGL(k_resample_small<kC2>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, copy_vec,
+                           fold_vec, a, st_ws, st_user, n_w, n_part, anc);
+        break;
+    }
+    return check_launch("resample kernel (one launch)");
 }
 
 int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
                      hipStream_t stream)
 {
-    if (p.variant == kMegopolis && n <= kSmallMaxN) return enqueue_small(w, n, p, ws, st_user, anc, stream);
+    if (n <= (p.variant == kMegopolis ? kSmallMaxN : kSmallMaxNOther))
+        return enqueue_small(w, n, p, ws, st_user, anc, stream);
     int rc = enqueue_reduce_finalize(w, n, p, p.variant == kMegopolis, ws, st_user, stream);
     if (rc) return rc;
     return enqueue_loop(w, n, p, ws, anc, stream);

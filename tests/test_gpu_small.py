@@ -1,9 +1,10 @@
-"""The one-launch Megopolis path of mgp_resample for small filters
-(n <= 8192): bit-exact ancestors against the oracle across sizes, B on both
+"""The one-launch path of mgp_resample for small filters (n <= 8192 for
+Megopolis, n <= 4096 for the other variants): bit-exact ancestors against
+the oracle across sizes on both sides of the limits; for Megopolis B on both
 sides of the 20-step rounds and of the 4000-offset passes, 32- and 64-wide
-segments; stats bit-identical to the three-launch reduction (mgp_compute_B)
-for aligned and unaligned weights; invalid weights; and the workspace left
-unusable for mgp_resample_prepared."""
+segments; for C1/C2 two partition sizes; stats bit-identical to the
+three-launch reduction (mgp_compute_B) for aligned and unaligned weights;
+invalid weights; and the workspace left unusable for mgp_resample_prepared."""
 import numpy as np
 import pytest
 
@@ -42,6 +43,24 @@ def test_ancestors_match_oracle(env, n):
             assert st["B"] == B and st["status"] == 0 and st["n"] == n
 
 
+@pytest.mark.parametrize("variant", ["metropolis", "c1", "c2"])
+@pytest.mark.parametrize("n", [1, 2, 31, 100, 4095, 4101, SMALL_MAX])
+def test_other_variants_match_oracle(env, variant, n):
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 2.5, 41)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    for B in (1, 7, 64):
+        for ps in ((128, 512) if variant != "metropolis" else (128,)):
+            got = r.resample(wd, variant, B=B, seed=70 + B, stream_id=5, partition_bytes=ps).cpu().numpy()
+            ref = oracle.resample(w, variant, B, 70 + B, stream_id=5, partition_bytes=ps)
+            np.testing.assert_array_equal(got, ref, err_msg=f"{variant} n={n} B={B} ps={ps}")
+    got = r.resample(wd, variant, epsilon=0.01, seed=3).cpu().numpy()
+    B = r.last_stats()["B"]
+    assert B == oracle.B_from_weights(w, 0.01)[0]
+    np.testing.assert_array_equal(got, oracle.resample(w, variant, B, 3))
+
+
 def test_two_offset_passes_with_epsilon_and_clamp(env):
     """B from epsilon clamped to b_max = 8003: two full passes of 4000
     offsets and a tail of 3."""
@@ -58,8 +77,9 @@ def test_two_offset_passes_with_epsilon_and_clamp(env):
     np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", 8003, 3))
 
 
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis"])
 @pytest.mark.parametrize("n,shift", [(4096, 0), (4096, 1), (4101, 0), (SMALL_MAX, 0), (SMALL_MAX - 3, 1)])
-def test_stats_equal_three_launch_reduction(env, n, shift):
+def test_stats_equal_three_launch_reduction(env, variant, n, shift):
     """The fused kernel repeats k_reduce's chunks and thread mapping (float4
     or scalar, by the weights' alignment), so every stats field, the fp64 sum
     included, equals what mgp_compute_B writes for the same weights."""
@@ -70,9 +90,9 @@ def test_stats_equal_three_launch_reduction(env, n, shift):
     wd.copy_(torch.from_numpy(w))
     assert (wd.data_ptr() % 16 == 0) == (shift == 0)
     r = mgp.Resampler(n)
-    r.resample(wd, "megopolis", epsilon=0.01, seed=11, stream_id=4)
+    r.resample(wd, variant, epsilon=0.01, seed=11, stream_id=4)
     fused = r.last_stats()
-    r.compute_B(wd, "megopolis", epsilon=0.01, seed=11, stream_id=4)
+    r.compute_B(wd, variant, epsilon=0.01, seed=11, stream_id=4)
     three = r.last_stats()
     assert fused == three
     B, _, _ = oracle.B_from_weights(w, 0.01)
@@ -81,20 +101,21 @@ def test_stats_equal_three_launch_reduction(env, n, shift):
     assert abs(fused["w_sum"] - s) <= 1e-12 * s
 
 
-def test_invalid_weights_and_prepared_refused(env):
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2"])
+def test_invalid_weights_and_prepared_refused(env, variant):
     torch, dev, mgp = env
     n = 1000
     w = inputs.gaussian_weights(n, 1.0, 2)
     w[400] = np.nan
     r = mgp.Resampler(n)
-    got = r.resample(torch.from_numpy(w).to(dev), "megopolis", epsilon=0.01, seed=1).cpu().numpy()
+    got = r.resample(torch.from_numpy(w).to(dev), variant, epsilon=0.01, seed=1).cpu().numpy()
     assert (got == -1).all() and r.last_stats()["status"] == mgp.MGP_EWEIGHTS
     # a valid call, then a prepared loop with the same params: the one-launch
     # path leaves no offsets or mirror in the workspace, so the loop refuses
     w = inputs.gaussian_weights(n, 1.0, 2)
     wd = torch.from_numpy(w).to(dev)
-    r.resample(wd, "megopolis", B=7, seed=1)
-    assert (r.resample_prepared(wd, "megopolis", B=7, seed=1).cpu().numpy() == -1).all()
+    r.resample(wd, variant, B=7, seed=1)
+    assert (r.resample_prepared(wd, variant, B=7, seed=1).cpu().numpy() == -1).all()
 
 
 def test_first_size_past_the_limit_uses_three_launches(env):
