@@ -161,6 +161,121 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
     if (i < m) anc[i] = (int32_t)k;
 }
 
+// Megopolis over the mirrored weights for mid-size n, with each particle's
+// draws spread over four lanes. A block serves 64 particles: in each pass of
+// kSplitPass steps its four waves compute the particles' u draws (one Philox
+// call per five steps), their candidates' mirror positions and candidate
+// weights, all independent of the chain, into LDS; then wave 0 runs the
+// chains, whose serial part is only the product, the compare and two selects
+// per step. Every load of a pass is issued before the first LDS store, and
+// steps past the pass write a spare row, so nothing branches around a load.
+// The arithmetic and the draws are those of megopolis_mirror_chain_deep: the
+// ancestors are identical.
+constexpr uint32_t kSplitMaxM = 1u << 15;  // beyond, four waves per 64 particles cost more than they hide
+constexpr uint32_t kSplitPass = 60;  // steps per pass: a multiple of 20 (chain rounds) and of 5 (u blocks)
+constexpr uint32_t kSplitGroups = kLoopThreads / 64u;
+constexpr uint32_t kSplitBlocksPerWave = kSplitPass / (5u * kSplitGroups);
+static_assert(kSplitPass % (5u * kSplitGroups) == 0 && kSplitPass % 20u == 0, "whole u blocks per wave and rounds");
+
+__global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* __restrict__ mirror, uint32_t n,
+                                                                  uint32_t m, const mgp_stats* __restrict__ st,
+                                                                  const uint32_t* __restrict__ offsets,
+                                                                  uint32_t key0, uint32_t key1, uint32_t stream_id,
+                                                                  uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
+                                                                  int32_t* __restrict__ anc)
+{
+    __shared__ float su[kSplitPass + 1][64];   // row kSplitPass: the spare row
+    __shared__ float swj[kSplitPass + 1][64];
+    __shared__ uint32_t sjb[kSplitPass + 1][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    // the wave's index, known to the compiler as wave-uniform: its offsets
+    // are scalar loads
+    const uint32_t q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t i = blockIdx.x * 64u + lane;
+    const uint32_t B = st->B;
+    const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    if (!ok) {
+        if (q == 0 && i < m) anc[i] = -1;
+        return;
+    }
+    // lanes past m run too (the mirror's padding keeps their loads in bounds)
+    const char* M = reinterpret_cast<const char*>(mirror);
+    const uint32_t ia4 = (i & ~seg_mask) * 4u;
+    const uint32_t il4 = (i & seg_mask) * 4u;
+    uint32_t kk = i * 4u;
+    float wk = *reinterpret_cast<const float*>(M + i * 4u);
+    for (uint32_t b0 = 0; b0 < B; b0 += kSplitPass) {
+        const uint32_t cnt = B - b0 < kSplitPass ? B - b0 : kSplitPass;
+        // this wave's u blocks q, q + 4, ... of the pass: draws, positions and
+        // candidate weights (steps past the pass use step cnt - 1's offset and
+        // land in the spare row)
+        UBlock ub[kSplitBlocksPerWave];
+        uint32_t jb[kSplitBlocksPerWave][5];
+        float wj[kSplitBlocksPerWave][5];
+#pragma unroll
+        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t) {
+            const uint32_t g = q + kSplitGroups * t;
+#pragma unroll
+            for (uint32_t r = 0; r < 5u; ++r) {
+                const uint32_t s = g * 5u + r;
+                uint32_t o = offsets[b0 + (s < cnt ? s : cnt - 1u)];
+                o = o < n ? o : n - 1u;
+                const uint32_t oa4 = (o & ~seg_mask) * 4u;
+                const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
+                wj[t][r] = *reinterpret_cast<const float*>(M + oa4 + voff);
+                jb[t][r] = voff + oa4;
+            }
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t)
+            ub[t] = u_block(philox(b0 / 5u + q + kSplitGroups * t, kTagU, stream_id, i, key0, key1));
+#pragma unroll
+        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t) {
+#pragma unroll
+            for (uint32_t r = 0; r < 5u; ++r) {
+                const uint32_t s = (q + kSplitGroups * t) * 5u + r;
+                const uint32_t row = s < cnt ? s : kSplitPass;
+                su[row][lane] = ub[t].u[r];
+                swj[row][lane] = wj[t][r];
+                sjb[row][lane] = jb[t][r];
+            }
+        }
+        __syncthreads();
+        if (q == 0) {
+            uint32_t s0 = 0;
+            for (; s0 + 20u <= cnt; s0 += 20u) {
+                float uu[20], ww[20];
+                uint32_t jj[20];
+#pragma unroll
+                for (uint32_t s = 0; s < 20u; ++s) {
+                    uu[s] = su[s0 + s][lane];
+                    ww[s] = swj[s0 + s][lane];
+                    jj[s] = sjb[s0 + s][lane];
+                }
+#pragma unroll
+                for (uint32_t s = 0; s < 20u; ++s) {
+                    const float prod = uu[s] * wk;
+                    const bool acc = prod <= ww[s];
+                    kk = acc ? jj[s] : kk;
+                    wk = acc ? ww[s] : wk;
+                }
+            }
+            for (; s0 < cnt; ++s0) {
+                const float prod = su[s0][lane] * wk;
+                const float w = swj[s0][lane];
+                const bool acc = prod <= w;
+                kk = acc ? sjb[s0][lane] : kk;
+                wk = acc ? w : wk;
+            }
+        }
+        __syncthreads();  // the next pass overwrites the buffers
+    }
+    if (q == 0 && i < m) {
+        const uint32_t k = kk / 4u;
+        anc[i] = (int32_t)(k >= n ? k - n : k);
+    }
+}
+
 // Megopolis (Algorithm 5, B by eq. (proposition) of Section 4.1) for a small
 // filter in one launch (mgp_resample, n <= kSmallMaxN).
 // Every block copies the weights into LDS as the mirror M[k] = w[k mod n],
@@ -542,10 +657,17 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
     const uint32_t cap = p.b_max;
     const uint32_t seg_mask = p.segment - 1u;
     if (uses_mirror(n, p.variant) && m <= n && m <= kDeepMaxM) {
-        // few waves: deep prefetch per particle instead of four particles per thread
+        // few waves: up to 2^15 outputs the draws spread over four lanes, above
+        // that twenty steps' loads per round trip, instead of four particles
+        // per thread
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
-        hipLaunchKernelGGL(k_megopolis_mirror_deep, grid, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs, k0, k1,
-                           p.stream_id, tag, cap, seg_mask, anc);
+        if (m <= kSplitMaxM) {
+            hipLaunchKernelGGL(k_megopolis_split, dim3((m + 63u) / 64u), dim3(kLoopThreads), 0, stream, mirror, n, m,
+                               st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc);
+        } else {
+            hipLaunchKernelGGL(k_megopolis_mirror_deep, grid, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs,
+                               k0, k1, p.stream_id, tag, cap, seg_mask, anc);
+        }
         return check_launch("megopolis kernel (small n)");
     }
     if (uses_mirror(n, p.variant) && m <= n) {

@@ -61,6 +61,25 @@ def test_other_variants_match_oracle(env, variant, n):
     np.testing.assert_array_equal(got, oracle.resample(w, variant, B, 3))
 
 
+@pytest.mark.parametrize("n", [SMALL_MAX + 1, 20000, 1 << 15, (1 << 15) + 1])
+def test_mid_size_chains(env, n):
+    """Past the one-launch limit: the three launches, whose accept loop up to
+    2^15 outputs spreads each particle's draws over four lanes in passes of 60
+    steps (B on both sides of the pass and round boundaries), and above runs
+    twenty steps' loads per round trip."""
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 3.0, 77)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    for B in (1, 19, 59, 60, 61, 121, 354):
+        got = r.resample(wd, "megopolis", B=B, seed=900 + B, stream_id=6).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", B, 900 + B, stream_id=6),
+                                      err_msg=f"n={n} B={B}")
+    m = n // 2 + 3  # M < N through the same kernels
+    got = r.resample_m(wd, m, "megopolis", B=61, seed=5).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.resample_m(w, m, "megopolis", 61, 5))
+
+
 def test_two_offset_passes_with_epsilon_and_clamp(env):
     """B from epsilon clamped to b_max = 8003: two full passes of 4000
     offsets and a tail of 3."""
