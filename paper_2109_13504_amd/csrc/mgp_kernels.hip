@@ -171,8 +171,8 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
 // steps past the pass write a spare row, so nothing branches around a load.
 // The arithmetic and the draws are those of megopolis_mirror_chain_deep: the
 // ancestors are identical.
-constexpr uint32_t kSplitMaxM = 1u << 15;  // beyond, four waves per 64 particles cost more than they hide
-constexpr uint32_t kSplitPass = 60;  // steps per pass: a multiple of 20 (chain rounds) and of 5 (u blocks)
+constexpr uint32_t kSplitMaxM = 1u << 16;  // beyond, four waves per 64 particles cost more than they hide
+constexpr uint32_t kSplitPass = 20;  // steps per pass: a multiple of 20 (chain rounds) and of 5 (u blocks)
 constexpr uint32_t kSplitGroups = kLoopThreads / 64u;
 constexpr uint32_t kSplitBlocksPerWave = kSplitPass / (5u * kSplitGroups);
 static_assert(kSplitPass % (5u * kSplitGroups) == 0 && kSplitPass % 20u == 0, "whole u blocks per wave and rounds");
@@ -657,7 +657,7 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
     const uint32_t cap = p.b_max;
     const uint32_t seg_mask = p.segment - 1u;
     if (uses_mirror(n, p.variant) && m <= n && m <= kDeepMaxM) {
-        // few waves: up to 2^15 outputs the draws spread over four lanes, above
+        // few waves: up to 2^16 outputs the draws spread over four lanes, above
         // that twenty steps' loads per round trip, instead of four particles
         // per thread
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));

@@ -61,17 +61,17 @@ def test_other_variants_match_oracle(env, variant, n):
     np.testing.assert_array_equal(got, oracle.resample(w, variant, B, 3))
 
 
-@pytest.mark.parametrize("n", [SMALL_MAX + 1, 20000, 1 << 15, (1 << 15) + 1])
+@pytest.mark.parametrize("n", [SMALL_MAX + 1, 20000, 1 << 16, (1 << 16) + 1])
 def test_mid_size_chains(env, n):
     """Past the one-launch limit: the three launches, whose accept loop up to
-    2^15 outputs spreads each particle's draws over four lanes in passes of 60
-    steps (B on both sides of the pass and round boundaries), and above runs
-    twenty steps' loads per round trip."""
+    2^16 outputs spreads each particle's draws over four lanes in passes of 20
+    steps (B on both sides of the pass boundaries), and above runs twenty
+    steps' loads per round trip."""
     torch, dev, mgp = env
     w = inputs.gaussian_weights(n, 3.0, 77)
     wd = torch.from_numpy(w).to(dev)
     r = mgp.Resampler(n)
-    for B in (1, 19, 59, 60, 61, 121, 354):
+    for B in (1, 19, 20, 21, 59, 60, 61, 354):
         got = r.resample(wd, "megopolis", B=B, seed=900 + B, stream_id=6).cpu().numpy()
         np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", B, 900 + B, stream_id=6),
                                       err_msg=f"n={n} B={B}")
