@@ -91,9 +91,10 @@ int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes);
  *      o_0..o_{B-1} (Algorithm 5) are generated here;
  *   3. the accept loop: ancestors_dev[i] = k_i for i in [0, n).
  * For n <= 8192 (MGP_MEGOPOLIS) or n <= 4096 (the other variants) the three
- * steps run as one launch that keeps the weights in LDS (same results, stats
- * included); it leaves nothing in the workspace for a following
- * mgp_resample_prepared, which only mgp_compute_B prepares.
+ * steps run as one launch that keeps the weights in LDS, and for MGP_MEGOPOLIS
+ * up to 32768 as two (step 2 inside the accept loop); the results, stats
+ * included, are the same. These leave nothing in the workspace for a
+ * following mgp_resample_prepared, which only mgp_compute_B prepares.
  * w_dev          : n fp32 weights, device, contiguous, >= 0 and finite.
  * ancestors_dev  : n int32, device, written.
  * stats_dev      : device mgp_stats written by step 2, or NULL.

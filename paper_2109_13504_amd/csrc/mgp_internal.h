@@ -85,9 +85,10 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
                    hipStream_t stream);
 int enqueue_gather(const float* states, uint32_t n_states, uint32_t d, const int32_t* anc, uint32_t n_out,
                    float* out, hipStream_t stream);
-// mgp_resample's work: one launch up to 8192 (Megopolis) or 4096 particles
-// (its workspace then holds nothing for a prepared loop), else the reduction
-// + finalize and the accept loop.
+// mgp_resample's work: one launch up to 8192 (Megopolis) or 4096 particles,
+// two up to 32768 (Megopolis: the finalize step inside the accept loop),
+// leaving nothing in the workspace for a prepared loop; else the reduction +
+// finalize and the accept loop.
 int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
                      hipStream_t stream);
 

@@ -161,6 +161,20 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
     if (i < m) anc[i] = (int32_t)k;
 }
 
+// What k_megopolis_split<true> needs to do the finalize step itself.
+struct SplitFinalize {
+    const Partial* parts;
+    uint32_t nparts;
+    FinalizeArgs a;
+    mgp_stats* st_ws;
+    mgp_stats* st_user;
+};
+
+constexpr uint32_t kSplitMaxM = 1u << 16;  // beyond, four waves per 64 particles cost more than they hide
+// mgp_resample up to this size does the finalize step inside the split loop
+// (beyond, its extra registers cost more than the launch it saves)
+constexpr uint32_t kSplitFusedMaxN = 1u << 15;
+
 // Megopolis over the mirrored weights for mid-size n, with each particle's
 // draws spread over four lanes. A block serves 64 particles: in each pass of
 // kSplitPass steps its four waves compute the particles' u draws (one Philox
@@ -171,18 +185,22 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
 // steps past the pass write a spare row, so nothing branches around a load.
 // The arithmetic and the draws are those of megopolis_mirror_chain_deep: the
 // ancestors are identical.
-constexpr uint32_t kSplitMaxM = 1u << 16;  // beyond, four waves per 64 particles cost more than they hide
+// With Fused (mgp_resample, n <= kSplitFusedMaxN) every block also does the
+// finalize step over the partials k_reduce wrote, and draws each pass's
+// offsets into LDS (waves 1-3 draw the next pass's while wave 0 runs the
+// chains), so the finalize launch goes.
 constexpr uint32_t kSplitPass = 20;  // steps per pass: a multiple of 20 (chain rounds) and of 5 (u blocks)
 constexpr uint32_t kSplitGroups = kLoopThreads / 64u;
 constexpr uint32_t kSplitBlocksPerWave = kSplitPass / (5u * kSplitGroups);
 static_assert(kSplitPass % (5u * kSplitGroups) == 0 && kSplitPass % 20u == 0, "whole u blocks per wave and rounds");
 
+template <bool Fused>
 __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* __restrict__ mirror, uint32_t n,
                                                                   uint32_t m, const mgp_stats* __restrict__ st,
                                                                   const uint32_t* __restrict__ offsets,
                                                                   uint32_t key0, uint32_t key1, uint32_t stream_id,
                                                                   uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
-                                                                  int32_t* __restrict__ anc)
+                                                                  int32_t* __restrict__ anc, SplitFinalize f)
 {
     __shared__ float su[kSplitPass + 1][64];   // row kSplitPass: the spare row
     __shared__ float swj[kSplitPass + 1][64];
@@ -192,8 +210,27 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
     // are scalar loads
     const uint32_t q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t i = blockIdx.x * 64u + lane;
-    const uint32_t B = st->B;
-    const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    __shared__ uint32_t soffs[2][Fused ? kSplitPass : 1];  // this pass's offsets and the next pass's
+    uint32_t B;
+    bool ok;
+    if constexpr (Fused) {
+        // the finalize step in every block, over the partials k_reduce wrote:
+        // B and the stats exactly as k_finalize computes them (block 0
+        // returns the stats; the workspace record is marked unusable for a
+        // prepared loop, which would find no offsets there)
+        __shared__ mgp_stats st_local;
+        B = finalize_one(f.parts, f.nparts, f.a, &st_local, blockIdx.x == 0 ? f.st_user : nullptr, nullptr);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            mgp_stats r = st_local;
+            r.n = 0;
+            r.tag = 0;
+            *f.st_ws = r;
+        }
+        ok = B > 0;
+    } else {
+        B = st->B;
+        ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    }
     if (!ok) {
         if (q == 0 && i < m) anc[i] = -1;
         return;
@@ -204,7 +241,23 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
     const uint32_t il4 = (i & seg_mask) * 4u;
     uint32_t kk = i * 4u;
     float wk = *reinterpret_cast<const float*>(M + i * 4u);
-    for (uint32_t b0 = 0; b0 < B; b0 += kSplitPass) {
+    // the offsets of the pass starting at step c0, drawn as k_finalize draws
+    // them, by the threads t0, t0 + stride, ... of the block
+    auto draw_offsets = [&](uint32_t c0, uint32_t* dst, uint32_t t0, uint32_t stride) {
+        const uint32_t cnt = B - c0 < kSplitPass ? B - c0 : kSplitPass;
+        for (uint32_t c = t0; c < (cnt + 3u) / 4u; c += stride) {
+            const Words x = philox(c0 / 4u + c, kTagOffset, stream_id, 0u, key0, key1);
+            const uint32_t o[4] = {x.x0, x.x1, x.x2, x.x3};
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                if (4u * c + r < cnt) dst[4u * c + r] = uniform_index(o[r], n);
+        }
+    };
+    if constexpr (Fused) {
+        draw_offsets(0u, soffs[0], threadIdx.x, kLoopThreads);
+        __syncthreads();
+    }
+    for (uint32_t b0 = 0, buf = 0; b0 < B; b0 += kSplitPass, buf ^= 1u) {
         const uint32_t cnt = B - b0 < kSplitPass ? B - b0 : kSplitPass;
         // this wave's u blocks q, q + 4, ... of the pass: draws, positions and
         // candidate weights (steps past the pass use step cnt - 1's offset and
@@ -218,7 +271,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
 #pragma unroll
             for (uint32_t r = 0; r < 5u; ++r) {
                 const uint32_t s = g * 5u + r;
-                uint32_t o = offsets[b0 + (s < cnt ? s : cnt - 1u)];
+                uint32_t o = Fused ? soffs[buf][s < cnt ? s : cnt - 1u] : offsets[b0 + (s < cnt ? s : cnt - 1u)];
                 o = o < n ? o : n - 1u;
                 const uint32_t oa4 = (o & ~seg_mask) * 4u;
                 const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
@@ -267,6 +320,10 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
                 kk = acc ? sjb[s0][lane] : kk;
                 wk = acc ? w : wk;
             }
+        } else if constexpr (Fused) {
+            // while wave 0 runs the chains, the other waves draw the next
+            // pass's offsets into the other buffer
+            if (b0 + kSplitPass < B) draw_offsets(b0 + kSplitPass, soffs[buf ^ 1u], threadIdx.x - 64u, kLoopThreads - 64u);
         }
         __syncthreads();  // the next pass overwrites the buffers
     }
@@ -593,12 +650,13 @@ size_t workspace_bytes(uint32_t n, const Params& p)
     return b;
 }
 
-int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,
-                            mgp_stats* st_user, hipStream_t stream)
+// The reduction launch of the three-launch path: partials (and, for
+// Megopolis with make_offsets, the mirror) in the workspace. Returns the
+// number of partials through *nparts.
+static int enqueue_reduce(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws, uint32_t* nparts,
+                          hipStream_t stream)
 {
     Partial* part = reinterpret_cast<Partial*>(ws + kWsPartialsOffset);
-    mgp_stats* st = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
-    uint32_t* offs = reinterpret_cast<uint32_t*>(ws + kWsOffsetsOffset);
     float* mirror = (make_offsets && uses_mirror(n, p.variant)) ? reinterpret_cast<float*>(ws + mirror_offset(p.b_max))
                                                                   : nullptr;
     const uint32_t g = reduce_blocks(n);
@@ -608,8 +666,12 @@ int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool ma
         hipLaunchKernelGGL(k_reduce<true>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part, mirror);
     else
         hipLaunchKernelGGL(k_reduce<false>, dim3(g), dim3(kReduceThreads), 0, stream, w, n, chunk, part, mirror);
-    int rc = check_launch("reduce kernel");
-    if (rc) return rc;
+    *nparts = g;
+    return check_launch("reduce kernel");
+}
+
+static FinalizeArgs finalize_args(uint32_t n, const Params& p, bool make_offsets)
+{
     FinalizeArgs a;
     a.n = n;
     a.eps = p.eps;
@@ -620,6 +682,19 @@ int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool ma
     a.key1 = (uint32_t)(p.seed >> 32);
     a.stream_id = p.stream_id;
     a.tag = call_tag(n, p.variant, p.seed, p.stream_id);
+    return a;
+}
+
+int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,
+                            mgp_stats* st_user, hipStream_t stream)
+{
+    Partial* part = reinterpret_cast<Partial*>(ws + kWsPartialsOffset);
+    mgp_stats* st = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(ws + kWsOffsetsOffset);
+    uint32_t g = 0;
+    int rc = enqueue_reduce(w, n, p, make_offsets, ws, &g, stream);
+    if (rc) return rc;
+    const FinalizeArgs a = finalize_args(n, p, make_offsets);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kReduceThreads), 0, stream, part, g, a, st, st_user, offs);
     return check_launch("finalize kernel");
 }
@@ -662,8 +737,8 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
         // per thread
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
         if (m <= kSplitMaxM) {
-            hipLaunchKernelGGL(k_megopolis_split, dim3((m + 63u) / 64u), dim3(kLoopThreads), 0, stream, mirror, n, m,
-                               st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc);
+            hipLaunchKernelGGL(k_megopolis_split<false>, dim3((m + 63u) / 64u), dim3(kLoopThreads), 0, stream, mirror,
+                               n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, SplitFinalize{});
         } else {
             hipLaunchKernelGGL(k_megopolis_mirror_deep, grid, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs,
                                k0, k1, p.stream_id, tag, cap, seg_mask, anc);
@@ -707,16 +782,7 @@ int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_sta
     const bool aligned = ((uintptr_t)w & 15u) == 0;
     const uint32_t copy_vec = (aligned && n % 4u == 0) ? 1u : 0u;
     const uint32_t fold_vec = p.variant == kMegopolis ? copy_vec : (aligned ? 1u : 0u);
-    FinalizeArgs a;
-    a.n = n;
-    a.eps = p.eps;
-    a.B_user = p.B;
-    a.b_max = p.b_max;
-    a.make_offsets = 0u;
-    a.key0 = (uint32_t)p.seed;
-    a.key1 = (uint32_t)(p.seed >> 32);
-    a.stream_id = p.stream_id;
-    a.tag = call_tag(n, p.variant, p.seed, p.stream_id);
+    const FinalizeArgs a = finalize_args(n, p, false);
     mgp_stats* st_ws = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
     const dim3 grid((n + kLoopThreads - 1u) / kLoopThreads);
     const uint32_t n_w = p.partition_bytes / 4u;
@@ -747,6 +813,19 @@ int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_
 {
     if (n <= (p.variant == kMegopolis ? kSmallMaxN : kSmallMaxNOther))
         return enqueue_small(w, n, p, ws, st_user, anc, stream);
+    if (p.variant == kMegopolis && n <= kSplitFusedMaxN) {
+        // two launches: the reduction (partials and mirror), then the split
+        // accept loop with the finalize step done in every block
+        uint32_t g = 0;
+        int rc = enqueue_reduce(w, n, p, true, ws, &g, stream);
+        if (rc) return rc;
+        const SplitFinalize f{reinterpret_cast<const Partial*>(ws + kWsPartialsOffset), g, finalize_args(n, p, false),
+                              reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset), st_user};
+        const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
+        hipLaunchKernelGGL(k_megopolis_split<true>, dim3((n + 63u) / 64u), dim3(kLoopThreads), 0, stream, mirror, n, n,
+                           nullptr, nullptr, f.a.key0, f.a.key1, p.stream_id, f.a.tag, p.b_max, p.segment - 1u, anc, f);
+        return check_launch("megopolis kernel (finalize and split loop)");
+    }
     int rc = enqueue_reduce_finalize(w, n, p, p.variant == kMegopolis, ws, st_user, stream);
     if (rc) return rc;
     return enqueue_loop(w, n, p, ws, anc, stream);

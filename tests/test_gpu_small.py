@@ -61,12 +61,13 @@ def test_other_variants_match_oracle(env, variant, n):
     np.testing.assert_array_equal(got, oracle.resample(w, variant, B, 3))
 
 
-@pytest.mark.parametrize("n", [SMALL_MAX + 1, 20000, 1 << 16, (1 << 16) + 1])
+@pytest.mark.parametrize("n", [SMALL_MAX + 1, 20000, 1 << 15, (1 << 15) + 1, 1 << 16, (1 << 16) + 1])
 def test_mid_size_chains(env, n):
-    """Past the one-launch limit: the three launches, whose accept loop up to
-    2^16 outputs spreads each particle's draws over four lanes in passes of 20
-    steps (B on both sides of the pass boundaries), and above runs twenty
-    steps' loads per round trip."""
+    """Past the one-launch limit: up to 2^15 the reduction launch and the split
+    accept loop with the finalize step inside; up to 2^16 the three launches
+    with the split loop (each particle's draws over four lanes in passes of 20
+    steps; B on both sides of the pass boundaries); above, twenty steps'
+    loads per round trip."""
     torch, dev, mgp = env
     w = inputs.gaussian_weights(n, 3.0, 77)
     wd = torch.from_numpy(w).to(dev)
@@ -78,6 +79,17 @@ def test_mid_size_chains(env, n):
     m = n // 2 + 3  # M < N through the same kernels
     got = r.resample_m(wd, m, "megopolis", B=61, seed=5).cpu().numpy()
     np.testing.assert_array_equal(got, oracle.resample_m(w, m, "megopolis", 61, 5))
+    # B from epsilon: up to 2^15 the finalize step runs inside the split loop
+    # kernel; the stats equal mgp_compute_B's, and the ancestors the oracle's
+    got = r.resample(wd, "megopolis", epsilon=0.01, seed=12, stream_id=2).cpu().numpy()
+    fused = r.last_stats()
+    r.compute_B(wd, "megopolis", epsilon=0.01, seed=12, stream_id=2)
+    assert fused == r.last_stats()
+    np.testing.assert_array_equal(got, oracle.resample(w, "megopolis", fused["B"], 12, stream_id=2))
+    bad = w.copy()
+    bad[n // 3] = -1.0
+    got = r.resample(torch.from_numpy(bad).to(dev), "megopolis", epsilon=0.01, seed=1).cpu().numpy()
+    assert (got == -1).all() and r.last_stats()["status"] == mgp.MGP_EWEIGHTS
 
 
 def test_two_offset_passes_with_epsilon_and_clamp(env):
