@@ -161,196 +161,21 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
     if (i < m) anc[i] = (int32_t)k;
 }
 
-// What k_megopolis_split<true> needs to do the finalize step itself.
-struct SplitFinalize {
-    const Partial* parts;
-    uint32_t nparts;
-    FinalizeArgs a;
-    mgp_stats* st_ws;
-    mgp_stats* st_user;
-};
 
-constexpr uint32_t kSplitMaxM = 1u << 16;  // beyond, four waves per 64 particles cost more than they hide
-// mgp_resample up to this size does the finalize step inside the split loop
-// (beyond, its extra registers cost more than the launch it saves)
-constexpr uint32_t kSplitFusedMaxN = 1u << 15;
-
-// Megopolis over the mirrored weights for mid-size n, with each particle's
-// draws spread over four lanes. A block serves 64 particles: in each pass of
-// kSplitPass steps its four waves compute the particles' u draws (one Philox
-// call per five steps), their candidates' mirror positions and candidate
-// weights, all independent of the chain, into LDS; then wave 0 runs the
-// chains, whose serial part is only the product, the compare and two selects
-// per step. Every load of a pass is issued before the first LDS store, and
-// steps past the pass write a spare row, so nothing branches around a load.
-// The arithmetic and the draws are those of megopolis_mirror_chain_deep: the
-// ancestors are identical.
-// With Fused (mgp_resample, n <= kSplitFusedMaxN) every block also does the
-// finalize step over the partials k_reduce wrote, and draws each pass's
-// offsets into LDS (waves 1-3 draw the next pass's while wave 0 runs the
-// chains), so the finalize launch goes.
-constexpr uint32_t kSplitPass = 20;  // steps per pass: a multiple of 20 (chain rounds) and of 5 (u blocks)
-constexpr uint32_t kSplitGroups = kLoopThreads / 64u;
-constexpr uint32_t kSplitBlocksPerWave = kSplitPass / (5u * kSplitGroups);
-static_assert(kSplitPass % (5u * kSplitGroups) == 0 && kSplitPass % 20u == 0, "whole u blocks per wave and rounds");
-
-template <bool Fused>
-__global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* __restrict__ mirror, uint32_t n,
-                                                                  uint32_t m, const mgp_stats* __restrict__ st,
-                                                                  const uint32_t* __restrict__ offsets,
-                                                                  uint32_t key0, uint32_t key1, uint32_t stream_id,
-                                                                  uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
-                                                                  int32_t* __restrict__ anc, SplitFinalize f)
-{
-    __shared__ float su[kSplitPass + 1][64];   // row kSplitPass: the spare row
-    __shared__ float swj[kSplitPass + 1][64];
-    __shared__ uint32_t sjb[kSplitPass + 1][64];
-    const uint32_t lane = threadIdx.x & 63u;
-    // the wave's index, known to the compiler as wave-uniform: its offsets
-    // are scalar loads
-    const uint32_t q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t i = blockIdx.x * 64u + lane;
-    __shared__ uint32_t soffs[2][Fused ? kSplitPass : 1];  // this pass's offsets and the next pass's
-    uint32_t B;
-    bool ok;
-    if constexpr (Fused) {
-        // the finalize step in every block, over the partials k_reduce wrote:
-        // B and the stats exactly as k_finalize computes them (block 0
-        // returns the stats; the workspace record is marked unusable for a
-        // prepared loop, which would find no offsets there)
-        __shared__ mgp_stats st_local;
-        B = finalize_one(f.parts, f.nparts, f.a, &st_local, blockIdx.x == 0 ? f.st_user : nullptr, nullptr);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            mgp_stats r = st_local;
-            r.n = 0;
-            r.tag = 0;
-            *f.st_ws = r;
-        }
-        ok = B > 0;
-    } else {
-        B = st->B;
-        ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
-    }
-    if (!ok) {
-        if (q == 0 && i < m) anc[i] = -1;
-        return;
-    }
-    // lanes past m run too (the mirror's padding keeps their loads in bounds)
-    const char* M = reinterpret_cast<const char*>(mirror);
-    const uint32_t ia4 = (i & ~seg_mask) * 4u;
-    const uint32_t il4 = (i & seg_mask) * 4u;
-    uint32_t kk = i * 4u;
-    float wk = *reinterpret_cast<const float*>(M + i * 4u);
-    // the offsets of the pass starting at step c0, drawn as k_finalize draws
-    // them, by the threads t0, t0 + stride, ... of the block
-    auto draw_offsets = [&](uint32_t c0, uint32_t* dst, uint32_t t0, uint32_t stride) {
-        const uint32_t cnt = B - c0 < kSplitPass ? B - c0 : kSplitPass;
-        for (uint32_t c = t0; c < (cnt + 3u) / 4u; c += stride) {
-            const Words x = philox(c0 / 4u + c, kTagOffset, stream_id, 0u, key0, key1);
-            const uint32_t o[4] = {x.x0, x.x1, x.x2, x.x3};
-#pragma unroll
-            for (uint32_t r = 0; r < 4; ++r)
-                if (4u * c + r < cnt) dst[4u * c + r] = uniform_index(o[r], n);
-        }
-    };
-    if constexpr (Fused) {
-        draw_offsets(0u, soffs[0], threadIdx.x, kLoopThreads);
-        __syncthreads();
-    }
-    for (uint32_t b0 = 0, buf = 0; b0 < B; b0 += kSplitPass, buf ^= 1u) {
-        const uint32_t cnt = B - b0 < kSplitPass ? B - b0 : kSplitPass;
-        // this wave's u blocks q, q + 4, ... of the pass: draws, positions and
-        // candidate weights (steps past the pass use step cnt - 1's offset and
-        // land in the spare row)
-        UBlock ub[kSplitBlocksPerWave];
-        uint32_t jb[kSplitBlocksPerWave][5];
-        float wj[kSplitBlocksPerWave][5];
-#pragma unroll
-        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t) {
-            const uint32_t g = q + kSplitGroups * t;
-#pragma unroll
-            for (uint32_t r = 0; r < 5u; ++r) {
-                const uint32_t s = g * 5u + r;
-                uint32_t o = Fused ? soffs[buf][s < cnt ? s : cnt - 1u] : offsets[b0 + (s < cnt ? s : cnt - 1u)];
-                o = o < n ? o : n - 1u;
-                const uint32_t oa4 = (o & ~seg_mask) * 4u;
-                const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
-                wj[t][r] = *reinterpret_cast<const float*>(M + oa4 + voff);
-                jb[t][r] = voff + oa4;
-            }
-        }
-#pragma unroll
-        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t)
-            ub[t] = u_block(philox(b0 / 5u + q + kSplitGroups * t, kTagU, stream_id, i, key0, key1));
-#pragma unroll
-        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t) {
-#pragma unroll
-            for (uint32_t r = 0; r < 5u; ++r) {
-                const uint32_t s = (q + kSplitGroups * t) * 5u + r;
-                const uint32_t row = s < cnt ? s : kSplitPass;
-                su[row][lane] = ub[t].u[r];
-                swj[row][lane] = wj[t][r];
-                sjb[row][lane] = jb[t][r];
-            }
-        }
-        __syncthreads();
-        if (q == 0) {
-            uint32_t s0 = 0;
-            for (; s0 + 20u <= cnt; s0 += 20u) {
-                float uu[20], ww[20];
-                uint32_t jj[20];
-#pragma unroll
-                for (uint32_t s = 0; s < 20u; ++s) {
-                    uu[s] = su[s0 + s][lane];
-                    ww[s] = swj[s0 + s][lane];
-                    jj[s] = sjb[s0 + s][lane];
-                }
-#pragma unroll
-                for (uint32_t s = 0; s < 20u; ++s) {
-                    const float prod = uu[s] * wk;
-                    const bool acc = prod <= ww[s];
-                    kk = acc ? jj[s] : kk;
-                    wk = acc ? ww[s] : wk;
-                }
-            }
-            for (; s0 < cnt; ++s0) {
-                const float prod = su[s0][lane] * wk;
-                const float w = swj[s0][lane];
-                const bool acc = prod <= w;
-                kk = acc ? sjb[s0][lane] : kk;
-                wk = acc ? w : wk;
-            }
-        } else if constexpr (Fused) {
-            // while wave 0 runs the chains, the other waves draw the next
-            // pass's offsets into the other buffer
-            if (b0 + kSplitPass < B) draw_offsets(b0 + kSplitPass, soffs[buf ^ 1u], threadIdx.x - 64u, kLoopThreads - 64u);
-        }
-        __syncthreads();  // the next pass overwrites the buffers
-    }
-    if (q == 0 && i < m) {
-        const uint32_t k = kk / 4u;
-        anc[i] = (int32_t)(k >= n ? k - n : k);
-    }
-}
-
-// Megopolis (Algorithm 5, B by eq. (proposition) of Section 4.1) for a small
-// filter in one launch (mgp_resample, n <= kSmallMaxN).
-// Every block copies the weights into LDS as the mirror M[k] = w[k mod n],
-// repeats the reduction of k_reduce and k_finalize chunk by chunk in the
-// same order (so the fp64 sum, B and the stats are bit-identical to the
-// three-launch path), draws the offsets into LDS kSmallOffsets at a time,
-// and runs the chains of its own particles against the LDS mirror, twenty
-// steps' loads per round as in k_megopolis_mirror_deep. For small n the
-// three-launch path is two kernel gaps, a finalize and B/20 round trips to
-// L2; here it is one launch and LDS round trips.
+// mgp_resample of a small filter in one launch (Megopolis up to kSmallMaxN
+// particles, the other variants up to kSmallMaxNOther): every block copies
+// the weights into LDS as the mirror M[k] = w[k mod n] and repeats the
+// reduction of k_reduce and k_finalize chunk by chunk in the same order (so
+// the fp64 sum, B and the stats are bit-identical to the three-launch path,
+// B by eq. (proposition) of Section 4.1), then runs the chains of its own
+// particles against LDS: k_megopolis_split<kSplitSmall> for Megopolis
+// (Algorithm 5), k_resample_small for Algorithms 2-4.
 constexpr uint32_t kSmallMaxN = 8192;
 constexpr uint32_t kSmallMaxNOther = 4096;  // Metropolis, C1, C2: chains without shared indices gain less
 constexpr uint32_t kSmallPad = 512;       // lanes past n: slot <= n + 255 + n - 1 + 63 < 2n + 512
-constexpr uint32_t kSmallOffsets = 4000;  // a multiple of 4 (offset calls), 5 (u blocks) and 20 (rounds)
 constexpr uint32_t kSmallMaxParts = kSmallMaxN / kReduceChunk;
 static_assert(kSmallMaxN % kReduceChunk == 0 && kSmallMaxN <= (uint64_t)kReduceChunk * kMaxPartials,
               "the reduction of a small filter has at most kSmallMaxParts chunks");
-static_assert(kSmallOffsets % 20 == 0, "offset passes must start on a round boundary");
 
 // The first steps of the one-launch kernels: the LDS mirror
 // M[k] = w[k mod n], k < 2n + kSmallPad, then the reduction and B exactly as
@@ -432,94 +257,199 @@ __device__ __forceinline__ uint32_t small_prologue(const float* __restrict__ w, 
     return B;
 }
 
-__global__ __launch_bounds__(kLoopThreads) void k_megopolis_small(const float* __restrict__ w, uint32_t n,
-                                                                  uint32_t nparts, uint32_t chunk, uint32_t vec,
-                                                                  FinalizeArgs a, mgp_stats* __restrict__ st_ws,
-                                                                  mgp_stats* __restrict__ st_user, uint32_t seg_mask,
-                                                                  int32_t* __restrict__ anc)
+// The split loop's modes: the B, stats and offsets of a preceding k_finalize
+// (kSplitPrepared); the finalize step inside every block over the partials
+// of a preceding k_reduce (kSplitFinalize); or, for n <= kSmallMaxN, the whole
+// of mgp_resample in one launch with the weights in an LDS mirror
+// (kSplitSmall, with small_prologue).
+constexpr int kSplitPrepared = 0, kSplitFinalize = 1, kSplitSmall = 2;
+
+// What the split loop needs beyond the prepared workspace.
+struct SplitArgs {
+    const Partial* parts;  // kSplitFinalize: the reduction's partials
+    uint32_t nparts;       // kSplitFinalize, kSplitSmall
+    FinalizeArgs a;        // kSplitFinalize, kSplitSmall
+    mgp_stats* st_ws;      // kSplitFinalize, kSplitSmall: the workspace record, marked unusable
+    mgp_stats* st_user;    // kSplitFinalize, kSplitSmall: the caller's stats or null
+    const float* w;        // kSplitSmall: the weights
+    uint32_t chunk;        // kSplitSmall: weights per reduction chunk
+    uint32_t copy_vec;     // kSplitSmall: float4 copies into LDS
+    uint32_t fold_vec;     // kSplitSmall: float4 folds in the reduction
+};
+
+constexpr uint32_t kSplitMaxM = 1u << 16;  // beyond, four waves per 64 particles cost more than they hide
+// mgp_resample up to this size does the finalize step inside the split loop
+// (beyond, its extra registers cost more than the launch it saves)
+constexpr uint32_t kSplitFusedMaxN = 1u << 15;
+
+// Megopolis over the mirrored weights for n up to kSplitMaxM, with each
+// particle's draws spread over four lanes. A block serves 64 particles: in each pass of
+// kSplitPass steps its four waves compute the particles' u draws (one Philox
+// call per five steps), their candidates' mirror positions and candidate
+// weights, all independent of the chain, into LDS; then wave 0 runs the
+// chains, whose serial part is only the product, the compare and two selects
+// per step. Every load of a pass is issued before the first LDS store, and
+// steps past the pass write a spare row, so nothing branches around a load.
+// The arithmetic and the draws are those of megopolis_mirror_chain_deep: the
+// ancestors are identical.
+// In modes kSplitFinalize (mgp_resample, n <= kSplitFusedMaxN) and
+// kSplitSmall every block finds B itself and draws each pass's offsets into
+// LDS (waves 1-3 draw the next pass's while wave 0 runs the chains), so the
+// finalize launch goes; kSplitSmall also reads the candidates from its LDS
+// mirror.
+constexpr uint32_t kSplitPass = 20;  // steps per pass: a multiple of 20 (chain rounds) and of 5 (u blocks)
+constexpr uint32_t kSplitGroups = kLoopThreads / 64u;
+constexpr uint32_t kSplitBlocksPerWave = kSplitPass / (5u * kSplitGroups);
+static_assert(kSplitPass % (5u * kSplitGroups) == 0 && kSplitPass % 20u == 0, "whole u blocks per wave and rounds");
+
+template <int Mode>
+__global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* __restrict__ mirror, uint32_t n,
+                                                                  uint32_t m, const mgp_stats* __restrict__ st,
+                                                                  const uint32_t* __restrict__ offsets,
+                                                                  uint32_t key0, uint32_t key1, uint32_t stream_id,
+                                                                  uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
+                                                                  int32_t* __restrict__ anc, SplitArgs f)
 {
-    __shared__ __align__(16) float M[2 * kSmallMaxN + kSmallPad];
-    __shared__ uint32_t offs[kSmallOffsets];
-    __shared__ Partial parts[kSmallMaxParts];
-    __shared__ mgp_stats st_local;
-    const uint32_t B = small_prologue(w, n, nparts, chunk, vec, vec, a, st_ws, st_user, M, parts, &st_local);
-    const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
-    if (B == 0) {  // invalid weights
-        if (i < n) anc[i] = -1;
+    __shared__ float su[kSplitPass + 1][64];   // row kSplitPass: the spare row
+    __shared__ float swj[kSplitPass + 1][64];
+    __shared__ uint32_t sjb[kSplitPass + 1][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    // the wave's index, known to the compiler as wave-uniform: its offsets
+    // are scalar loads
+    const uint32_t q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t i = blockIdx.x * 64u + lane;
+    constexpr bool kOwnOffsets = Mode != kSplitPrepared;
+    __shared__ uint32_t soffs[2][kOwnOffsets ? kSplitPass : 1];  // this pass's offsets and the next pass's
+    __shared__ __align__(16) float Ms[Mode == kSplitSmall ? 2 * kSmallMaxN + kSmallPad : 1];
+    uint32_t B;
+    bool ok;
+    if constexpr (Mode == kSplitSmall) {
+        // the weights into the LDS mirror, the reduction and B (small_prologue)
+        __shared__ Partial parts[kSmallMaxParts];
+        __shared__ mgp_stats st_local;
+        B = small_prologue(f.w, n, f.nparts, f.chunk, f.copy_vec, f.fold_vec, f.a, f.st_ws, f.st_user, Ms, parts,
+                           &st_local);
+        ok = B > 0;
+    } else if constexpr (Mode == kSplitFinalize) {
+        // the finalize step in every block, over the partials k_reduce wrote:
+        // B and the stats exactly as k_finalize computes them (block 0
+        // returns the stats; the workspace record is marked unusable for a
+        // prepared loop, which would find no offsets there)
+        __shared__ mgp_stats st_local;
+        B = finalize_one(f.parts, f.nparts, f.a, &st_local, blockIdx.x == 0 ? f.st_user : nullptr, nullptr);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            mgp_stats r = st_local;
+            r.n = 0;
+            r.tag = 0;
+            *f.st_ws = r;
+        }
+        ok = B > 0;
+    } else {
+        B = st->B;
+        ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
+    }
+    if (!ok) {
+        if (q == 0 && i < m) anc[i] = -1;
         return;
     }
-    // 4. the chains; lanes past n run too, in bounds thanks to the padding
+    // lanes past m run too (the mirror's padding keeps their loads in bounds)
+    const char* M = Mode == kSplitSmall ? reinterpret_cast<const char*>(Ms) : reinterpret_cast<const char*>(mirror);
     const uint32_t ia4 = (i & ~seg_mask) * 4u;
     const uint32_t il4 = (i & seg_mask) * 4u;
-    const char* Mb = reinterpret_cast<const char*>(M);
     uint32_t kk = i * 4u;
-    float wk = M[i];
-    for (uint32_t base = 0; base < B; base += kSmallOffsets) {
-        const uint32_t cnt = B - base < kSmallOffsets ? B - base : kSmallOffsets;
-        __syncthreads();  // every lane is done with the previous pass's offsets
-        for (uint32_t c = threadIdx.x; c < (cnt + 3u) / 4u; c += kLoopThreads) {
-            const Words x = philox(base / 4u + c, kTagOffset, a.stream_id, 0u, a.key0, a.key1);
+    float wk = *reinterpret_cast<const float*>(M + i * 4u);
+    // the offsets of the pass starting at step c0, drawn as k_finalize draws
+    // them, by the threads t0, t0 + stride, ... of the block
+    auto draw_offsets = [&](uint32_t c0, uint32_t* dst, uint32_t t0, uint32_t stride) {
+        const uint32_t cnt = B - c0 < kSplitPass ? B - c0 : kSplitPass;
+        for (uint32_t c = t0; c < (cnt + 3u) / 4u; c += stride) {
+            const Words x = philox(c0 / 4u + c, kTagOffset, stream_id, 0u, key0, key1);
             const uint32_t o[4] = {x.x0, x.x1, x.x2, x.x3};
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r)
-                if (4u * c + r < cnt) offs[4u * c + r] = uniform_index(o[r], n);
+                if (4u * c + r < cnt) dst[4u * c + r] = uniform_index(o[r], n);
         }
+    };
+    if constexpr (kOwnOffsets) {
+        draw_offsets(0u, soffs[0], threadIdx.x, kLoopThreads);
         __syncthreads();
-        uint32_t s0 = 0;
-        for (; s0 + 20u <= cnt; s0 += 20u) {
-            float wj[20];
-            uint32_t jb[20];
+    }
+    for (uint32_t b0 = 0, buf = 0; b0 < B; b0 += kSplitPass, buf ^= 1u) {
+        const uint32_t cnt = B - b0 < kSplitPass ? B - b0 : kSplitPass;
+        // this wave's u blocks q, q + 4, ... of the pass: draws, positions and
+        // candidate weights (steps past the pass use step cnt - 1's offset and
+        // land in the spare row)
+        UBlock ub[kSplitBlocksPerWave];
+        uint32_t jb[kSplitBlocksPerWave][5];
+        float wj[kSplitBlocksPerWave][5];
 #pragma unroll
-            for (uint32_t s = 0; s < 20u; ++s) {
-                const uint32_t o = offs[s0 + s];
+        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t) {
+            const uint32_t g = q + kSplitGroups * t;
+#pragma unroll
+            for (uint32_t r = 0; r < 5u; ++r) {
+                const uint32_t s = g * 5u + r;
+                uint32_t o = kOwnOffsets ? soffs[buf][s < cnt ? s : cnt - 1u] : offsets[b0 + (s < cnt ? s : cnt - 1u)];
+                o = o < n ? o : n - 1u;
                 const uint32_t oa4 = (o & ~seg_mask) * 4u;
                 const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
-                wj[s] = *reinterpret_cast<const float*>(Mb + oa4 + voff);
-                jb[s] = voff + oa4;
-            }
-#pragma unroll
-            for (uint32_t g = 0; g < 4u; ++g) {
-                const UBlock ub = u_block(philox((base + s0) / 5u + g, kTagU, a.stream_id, i, a.key0, a.key1));
-#pragma unroll
-                for (uint32_t s = 0; s < 5u; ++s) {
-                    const float prod = ub.u[s] * wk;
-                    const bool acc = prod <= wj[g * 5u + s];
-                    kk = acc ? jb[g * 5u + s] : kk;
-                    wk = acc ? wj[g * 5u + s] : wk;
-                }
+                wj[t][r] = *reinterpret_cast<const float*>(M + oa4 + voff);
+                jb[t][r] = voff + oa4;
             }
         }
-        for (; s0 < cnt; s0 += 5u) {
-            const uint32_t m5 = cnt - s0 < 5u ? cnt - s0 : 5u;
-            float wj[5];
-            uint32_t jb[5];
 #pragma unroll
-            for (uint32_t s = 0; s < 5u; ++s) {
-                if (s < m5) {
-                    const uint32_t o = offs[s0 + s];
-                    const uint32_t oa4 = (o & ~seg_mask) * 4u;
-                    const uint32_t voff = ia4 | ((il4 + (o & seg_mask) * 4u) & (seg_mask * 4u));
-                    wj[s] = *reinterpret_cast<const float*>(Mb + oa4 + voff);
-                    jb[s] = voff + oa4;
-                }
-            }
-            const UBlock ub = u_block(philox((base + s0) / 5u, kTagU, a.stream_id, i, a.key0, a.key1));
+        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t)
+            ub[t] = u_block(philox(b0 / 5u + q + kSplitGroups * t, kTagU, stream_id, i, key0, key1));
 #pragma unroll
-            for (uint32_t s = 0; s < 5u; ++s) {
-                if (s < m5) {
-                    const float prod = ub.u[s] * wk;
-                    const bool acc = prod <= wj[s];
-                    kk = acc ? jb[s] : kk;
-                    wk = acc ? wj[s] : wk;
-                }
+        for (uint32_t t = 0; t < kSplitBlocksPerWave; ++t) {
+#pragma unroll
+            for (uint32_t r = 0; r < 5u; ++r) {
+                const uint32_t s = (q + kSplitGroups * t) * 5u + r;
+                const uint32_t row = s < cnt ? s : kSplitPass;
+                su[row][lane] = ub[t].u[r];
+                swj[row][lane] = wj[t][r];
+                sjb[row][lane] = jb[t][r];
             }
         }
+        __syncthreads();
+        if (q == 0) {
+            uint32_t s0 = 0;
+            for (; s0 + 20u <= cnt; s0 += 20u) {
+                float uu[20], ww[20];
+                uint32_t jj[20];
+#pragma unroll
+                for (uint32_t s = 0; s < 20u; ++s) {
+                    uu[s] = su[s0 + s][lane];
+                    ww[s] = swj[s0 + s][lane];
+                    jj[s] = sjb[s0 + s][lane];
+                }
+#pragma unroll
+                for (uint32_t s = 0; s < 20u; ++s) {
+                    const float prod = uu[s] * wk;
+                    const bool acc = prod <= ww[s];
+                    kk = acc ? jj[s] : kk;
+                    wk = acc ? ww[s] : wk;
+                }
+            }
+            for (; s0 < cnt; ++s0) {
+                const float prod = su[s0][lane] * wk;
+                const float w = swj[s0][lane];
+                const bool acc = prod <= w;
+                kk = acc ? sjb[s0][lane] : kk;
+                wk = acc ? w : wk;
+            }
+        } else if constexpr (kOwnOffsets) {
+            // while wave 0 runs the chains, the other waves draw the next
+            // pass's offsets into the other buffer
+            if (b0 + kSplitPass < B) draw_offsets(b0 + kSplitPass, soffs[buf ^ 1u], threadIdx.x - 64u, kLoopThreads - 64u);
+        }
+        __syncthreads();  // the next pass overwrites the buffers
     }
-    if (i < n) {
+    if (q == 0 && i < m) {
         const uint32_t k = kk / 4u;
         anc[i] = (int32_t)(k >= n ? k - n : k);
     }
 }
+
 
 // Metropolis, C1 and C2 (Algorithms 2-4) for a small filter in one launch:
 // the same prologue, then each thread runs its particle's chain of k_resample
@@ -737,8 +667,8 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
         // per thread
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
         if (m <= kSplitMaxM) {
-            hipLaunchKernelGGL(k_megopolis_split<false>, dim3((m + 63u) / 64u), dim3(kLoopThreads), 0, stream, mirror,
-                               n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, SplitFinalize{});
+            hipLaunchKernelGGL(k_megopolis_split<kSplitPrepared>, dim3((m + 63u) / 64u), dim3(kLoopThreads), 0, stream,
+                               mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, SplitArgs{});
         } else {
             hipLaunchKernelGGL(k_megopolis_mirror_deep, grid, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs,
                                k0, k1, p.stream_id, tag, cap, seg_mask, anc);
@@ -771,9 +701,10 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
 }
 
 // mgp_resample with n <= kSmallMaxN (Megopolis) or kSmallMaxNOther: one
-// launch of k_megopolis_small or k_resample_small. The reduction uses the chunks, thread mapping and fold
-// width that enqueue_reduce_finalize uses for the same n, variant and weight
-// alignment (float4 folds need a 16-byte aligned w, and with a mirror n % 4 == 0).
+// launch of k_megopolis_split<kSplitSmall> or k_resample_small. The reduction
+// uses the chunks, thread mapping and fold width that enqueue_reduce_finalize
+// uses for the same n, variant and weight alignment (float4 folds need a
+// 16-byte aligned w, and with a mirror n % 4 == 0).
 int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
                   hipStream_t stream)
 {
@@ -788,10 +719,21 @@ int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_sta
     const uint32_t n_w = p.partition_bytes / 4u;
     const uint32_t n_part = (uint32_t)(((uint64_t)n + n_w - 1u) / n_w);
     switch (p.variant) {
-    case kMegopolis:
-        hipLaunchKernelGGL(k_megopolis_small, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, copy_vec, a,
-                           st_ws, st_user, p.segment - 1u, anc);
-        break;
+    case kMegopolis: {
+            SplitArgs f{};
+            f.nparts = g;
+            f.a = a;
+            f.st_ws = st_ws;
+            f.st_user = st_user;
+            f.w = w;
+            f.chunk = chunk;
+            f.copy_vec = copy_vec;
+            f.fold_vec = copy_vec;
+            hipLaunchKernelGGL(k_megopolis_split<kSplitSmall>, dim3((n + 63u) / 64u), dim3(kLoopThreads), 0, stream,
+                               nullptr, n, n, nullptr, nullptr, a.key0, a.key1, p.stream_id, a.tag, p.b_max,
+                               p.segment - 1u, anc, f);
+            break;
+        }
     case kMetropolis:
         hipLaunchKernelGGL(k_resample_small<kMetropolis>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk,
                            copy_vec, fold_vec, a, st_ws, st_user, n_w, n_part, anc);
@@ -819,11 +761,16 @@ int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_
         uint32_t g = 0;
         int rc = enqueue_reduce(w, n, p, true, ws, &g, stream);
         if (rc) return rc;
-        const SplitFinalize f{reinterpret_cast<const Partial*>(ws + kWsPartialsOffset), g, finalize_args(n, p, false),
-                              reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset), st_user};
+        SplitArgs f{};
+        f.parts = reinterpret_cast<const Partial*>(ws + kWsPartialsOffset);
+        f.nparts = g;
+        f.a = finalize_args(n, p, false);
+        f.st_ws = reinterpret_cast<mgp_stats*>(ws + kWsStatsOffset);
+        f.st_user = st_user;
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
-        hipLaunchKernelGGL(k_megopolis_split<true>, dim3((n + 63u) / 64u), dim3(kLoopThreads), 0, stream, mirror, n, n,
-                           nullptr, nullptr, f.a.key0, f.a.key1, p.stream_id, f.a.tag, p.b_max, p.segment - 1u, anc, f);
+        hipLaunchKernelGGL(k_megopolis_split<kSplitFinalize>, dim3((n + 63u) / 64u), dim3(kLoopThreads), 0, stream,
+                           mirror, n, n, nullptr, nullptr, f.a.key0, f.a.key1, p.stream_id, f.a.tag, p.b_max,
+                           p.segment - 1u, anc, f);
         return check_launch("megopolis kernel (finalize and split loop)");
     }
     int rc = enqueue_reduce_finalize(w, n, p, p.variant == kMegopolis, ws, st_user, stream);
