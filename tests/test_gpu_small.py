@@ -1,10 +1,11 @@
-"""The one-launch path of mgp_resample for small filters (n <= 8192 for
-Megopolis, n <= 4096 for the other variants): bit-exact ancestors against
-the oracle across sizes on both sides of the limits; for Megopolis B on both
-sides of the 20-step rounds and of the 4000-offset passes, 32- and 64-wide
-segments; for C1/C2 two partition sizes; stats bit-identical to the
-three-launch reduction (mgp_compute_B) for aligned and unaligned weights;
-invalid weights; and the workspace left unusable for mgp_resample_prepared."""
+"""The short paths of mgp_resample: one launch for small filters (n <= 8192
+for Megopolis, n <= 4096 for the other variants) and, for Megopolis, two
+launches up to 2^15 and the split accept loop up to 2^16. Bit-exact
+ancestors against the oracle across sizes on both sides of the limits; for
+Megopolis B on both sides of the 20-step passes, 32- and 64-wide segments;
+for C1/C2 two partition sizes; stats bit-identical to the three-launch
+reduction (mgp_compute_B) for aligned and unaligned weights; invalid
+weights; and the workspace left unusable for mgp_resample_prepared."""
 import numpy as np
 import pytest
 
@@ -93,8 +94,8 @@ def test_mid_size_chains(env, n):
 
 
 def test_two_offset_passes_with_epsilon_and_clamp(env):
-    """B from epsilon clamped to b_max = 8003: two full passes of 4000
-    offsets and a tail of 3."""
+    """B from epsilon clamped to b_max = 8003: 400 passes of 20 offsets and
+    a tail of 3, in one launch."""
     torch, dev, mgp = env
     n = 2048
     w = inputs.gaussian_weights(n, 4.0, 3)
