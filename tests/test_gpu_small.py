@@ -161,3 +161,31 @@ def test_first_size_past_the_limit_uses_three_launches(env):
     # and the prepared loop works after it, as before
     r.compute_B(wd, "megopolis", B=41, seed=2)
     np.testing.assert_array_equal(r.resample_prepared(wd, "megopolis", B=41, seed=2).cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("n", [4096, 20000, 50000, 1 << 20])
+def test_resample_captured_in_a_graph(env, n):
+    """mgp_resample enqueues kernels only (no memset, no allocation), so a
+    caller can capture it: the one-, two- and three-launch paths and the
+    four-particle loop, replayed with eager work and synchronisation between
+    the replays, each replay equal to the oracle."""
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 3.0, 88)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    anc = torch.full((n,), -7, dtype=torch.int32, device=dev)
+    r.resample(wd, "megopolis", B=40, seed=3, out=anc)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.resample(wd, "megopolis", B=40, seed=3, out=anc)
+    idx = np.unique(np.random.Generator(np.random.PCG64(n)).integers(0, n, 3000)).astype(np.int32)
+    ref = oracle.resample_subset(w, "megopolis", 40, 3, idx)
+    for rep in range(3):
+        anc.fill_(-7)
+        junk = torch.randn(1 << 18, device=dev).sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(anc.cpu().numpy()[idx], ref, err_msg=f"n={n} replay {rep}")
+        del junk
