@@ -121,8 +121,8 @@ def test_n2pow20_sweep(torch_dev, mgp, y):
 
 
 def test_n2pow24_sampled(torch_dev, mgp):
-    """N = 2^24, y = 4 (B ~ 353), Megopolis and Metropolis, gather D = 8, in
-    the benchmark's launch configuration."""
+    """N = 2^24, y = 4 (B ~ 353), every variant (C1/C2 at 128-byte
+    partitions), gather D = 8, in the benchmark's launch configuration."""
     torch, dev = torch_dev
     n, d = 1 << 24, 8
     w, st = inputs.gaussian_weights_and_states(n, 4.0, d, 0)
@@ -130,7 +130,7 @@ def test_n2pow24_sampled(torch_dev, mgp):
     r = mgp.Resampler(n)
     g = np.random.Generator(np.random.PCG64(24))
     sample = np.unique(np.concatenate([np.arange(64), np.arange(n - 64, n), g.integers(0, n, 600)])).astype(np.int32)
-    for variant in ("megopolis", "metropolis"):
+    for variant in ("megopolis", "metropolis", "c1", "c2"):
         anc_d = r.resample(wd, variant, epsilon=0.01, seed=2024)
         out = mgp.gather(sd, anc_d)
         stats = r.last_stats()
