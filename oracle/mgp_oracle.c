@@ -45,8 +45,8 @@
  *                  m = (x0 & 255) | (x1 & 255) << 8 | (x2 & 255) << 16 for r = 4
  *   U{0, n-1}    : floor(x * n / 2^32)
  *
- * Every function is a transcription of the paper's definition in the paper's
- * order, with no blocking, fusion or reordering.
+ * Each function computes what its definition states, one particle and one
+ * step at a time, with no blocking, fusion or reordering.
  */
 #include <math.h>
 #include <stddef.h>
@@ -149,16 +149,17 @@ void mgp_oracle_offsets(uint64_t seed, uint32_t stream_id, uint32_t n, uint32_t 
         o[b] = mgp_oracle_offset(seed, stream_id, n, b);
 }
 
-/* Megopolis candidate index (Algorithm 5): aligned particle index, plus the
- * aligned part of the offset, plus the offset inside the segment, all taken
- * mod N. The paper's segment is 32 wide (its warp); `segment` generalises it
- * (a power of two, e.g. 64 for a 64-lane wavefront). */
+/* Megopolis candidate index (Algorithm 5, Section 4). With segments of S
+ * consecutive weights (the paper's S is its 32-thread warp; `segment`, a power
+ * of two, allows e.g. 64 for a 64-lane wavefront), an offset o does two
+ * things to particle i: it moves i's segment floor(o / S) segments forward,
+ * and it rotates i's place inside the segment by o mod S. The candidate is
+ * that place in that segment, wrapped around the N weights. */
 uint32_t mgp_oracle_megopolis_index_s(uint32_t i, uint32_t o, uint32_t n, uint32_t segment)
 {
-    uint64_t i_aligned = (uint64_t)i - (uint64_t)(i % segment);
-    uint64_t o_aligned = (uint64_t)o - (uint64_t)(o % segment);
-    uint64_t o_unaligned = ((uint64_t)i + (uint64_t)o) % segment;
-    return (uint32_t)((i_aligned + o_aligned + o_unaligned) % (uint64_t)n);
+    uint64_t dest_segment = (uint64_t)(i / segment) + (uint64_t)(o / segment);
+    uint64_t place = ((uint64_t)(i % segment) + (uint64_t)(o % segment)) % segment;
+    return (uint32_t)((dest_segment * segment + place) % (uint64_t)n);
 }
 
 /* The paper's segment is its 32-thread warp. */
@@ -285,14 +286,17 @@ int mgp_oracle_resample_m(const float* w, int32_t n, int32_t m, int variant, uin
     return OR_OK;
 }
 
-/* Ancestors for a subset of particles only (each chain is independent). */
+/* Ancestors of the particles idx[0..count) only: the same chains as
+ * mgp_oracle_resample (each chain is independent of the others), with the
+ * Megopolis segment width `segment` (32, the paper's, or 64). */
 int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t B, uint64_t seed,
-                               uint32_t stream_id, uint32_t partition_bytes,
+                               uint32_t stream_id, uint32_t partition_bytes, uint32_t segment,
                                uint32_t* offsets_scratch, const int32_t* idx, int32_t count,
                                int32_t* ancestors)
 {
     int rc = check_common(variant, n, partition_bytes);
     if (rc) return rc;
+    if (segment != 32u && segment != 64u) return OR_EINVAL;
     if (variant == OR_MEGOPOLIS) {
         if (!offsets_scratch) return OR_EINVAL;
         mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
@@ -300,7 +304,7 @@ int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t 
     uint32_t n_w = partition_bytes / 4u;
     for (int32_t c = 0; c < count; ++c) {
         if (idx[c] < 0 || idx[c] >= n) return OR_EINVAL;
-        ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, 32u,
+        ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, segment,
                                  offsets_scratch, (uint32_t)idx[c], (uint32_t)idx[c], NULL);
     }
     return OR_OK;

@@ -48,6 +48,35 @@ def test_segment64_matches_oracle(env, n):
     assert not torch.equal(b, c)
 
 
+@pytest.mark.parametrize("n", [20000, 1 << 20])
+def test_segment64_resample_paths(env, n):
+    """mgp_resample with 64-wide segments on the sizes that run the split loop
+    with the finalize step inside (8192 < n <= 2^15: n = 20000, every
+    ancestor) and the four-particle mirrored kernel (n > 2^18: n = 2^20, the
+    first and last 256 particles and 2048 random ones through the oracle's
+    segment-aware subset)."""
+    torch, dev, mgp = env
+    w = inputs.gaussian_weights(n, 3.0, 11)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    for seed in (3, 4):
+        anc = r.resample(wd, "megopolis", epsilon=0.01, seed=seed, stream_id=6, segment=64).cpu().numpy()
+        B = r.last_stats()["B"]
+        if n <= 1 << 15:
+            ref = oracle.resample_m(w, n, "megopolis", B, seed, stream_id=6, segment=64)
+            np.testing.assert_array_equal(anc, ref, err_msg=f"n={n} seed={seed}")
+        else:
+            g = np.random.Generator(np.random.PCG64(seed))
+            idx = np.unique(np.concatenate([np.arange(256), np.arange(n - 256, n),
+                                            g.integers(0, n, 2048)])).astype(np.int32)
+            ref = oracle.resample_subset(w, "megopolis", B, seed, idx, stream_id=6, segment=64)
+            np.testing.assert_array_equal(anc[idx], ref, err_msg=f"n={n} seed={seed}")
+        # the compute_B + prepared loop path gives the same ancestors
+        r.compute_B(wd, "megopolis", epsilon=0.01, seed=seed, stream_id=6, segment=64)
+        prep = r.resample_prepared(wd, "megopolis", epsilon=0.01, seed=seed, stream_id=6, segment=64)
+        np.testing.assert_array_equal(prep.cpu().numpy(), anc)
+
+
 def test_bad_segment_rejected(env):
     torch, dev, mgp = env
     r = mgp.Resampler(64)

@@ -1,7 +1,10 @@
 """Serving on the GPU: each request's ancestors and gathered states are the
 same when it runs alone and when it runs in a mix of concurrent requests,
 and equal the oracle; a tight HBM budget makes requests queue but all
-complete within the budget."""
+complete within the budget. The serving workload's own request sizes
+(N = round(2^U(12, 22)), y ~ U[0, 4], D = 16, five requests in
+[2^21, 2^22]) are checked alone, mixed and against the oracle's chains on
+sampled particles, for every variant."""
 import threading
 import time
 
@@ -71,6 +74,61 @@ def run_mixed(srv, reqs):
         out.append((res["B"], *srv.outputs(t, res)))
         srv.release(t)
     return out
+
+
+@pytest.fixture(scope="module")
+def workload_requests(env):
+    """24 requests drawn with the serving workload's recipe; the seed gives
+    five of them 2^21-2^22 particles (the largest 4,179,843)."""
+    torch, dev, _ = env
+    d = 16
+    g = np.random.Generator(np.random.PCG64(34))
+    sizes = np.rint(2.0 ** g.uniform(12.0, 22.0, 24)).astype(int)
+    ys = g.uniform(0.0, 4.0, 24)
+    assert (sizes >= 1 << 21).sum() >= 3 and sizes.max() <= 1 << 22
+    reqs = []
+    for k, (n, y) in enumerate(zip(sizes, ys)):
+        w, st = inputs.gaussian_weights_and_states(int(n), float(y), d, 300 + k)
+        reqs.append({"w": torch.from_numpy(w).to(dev), "w_np": w, "st_np": st, "seed": 7000 + k,
+                     "stream_id": 40 + k, "states": torch.from_numpy(st).to(dev), "y": float(y)})
+    return reqs
+
+
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2"])
+def test_workload_sizes_alone_mixed_oracle(env, workload_requests, variant):
+    """Requests of the serving workload's sizes (up to 2^22 particles, D = 16):
+    alone == mixed over every ancestor and gathered row; B equals the
+    oracle's eq. (proposition) value; the first and last 64 particles and 512
+    random ones equal the oracle's chains, and their gathered rows the
+    oracle's particle copy."""
+    torch, dev, mgp = env
+    d = 16
+    reqs = workload_requests
+    srv = mgp.Server(variant, d=d, hbm_budget=16 << 30, streams=4, max_batch=8)
+    alone = run_alone(srv, reqs)
+    mixed = run_mixed(srv, reqs)
+    st = srv.stats()
+    assert st["completed"] == 2 * len(reqs) and st["pool_in_use"] == 0
+    srv.close()
+    g = np.random.Generator(np.random.PCG64(55))
+    for k, r in enumerate(reqs):
+        n = r["w_np"].size
+        B = alone[k][0]
+        assert mixed[k][0] == B, f"request {k}"
+        np.testing.assert_array_equal(alone[k][1], mixed[k][1], err_msg=f"request {k} (n={n})")
+        np.testing.assert_array_equal(alone[k][2], mixed[k][2], err_msg=f"request {k} (n={n})")
+        ost = oracle.reduce(r["w_np"])
+        ob, raw, _ = oracle.choose_B(ost.w_sum, ost.w_max, n, 0.01)
+        if abs(raw - round(raw)) > 1e-9:
+            assert ob == B, f"request {k}: B {B} vs oracle {ob}"
+        idx = np.unique(np.concatenate([np.arange(min(64, n)), np.arange(max(0, n - 64), n),
+                                        g.integers(0, n, 512)])).astype(np.int32)
+        ref = oracle.resample_subset(r["w_np"], variant, B, r["seed"], idx, stream_id=r["stream_id"])
+        np.testing.assert_array_equal(alone[k][1][idx], ref, err_msg=f"request {k} (n={n}, y={r['y']:.2f})")
+        np.testing.assert_array_equal(alone[k][2][idx], oracle.gather(r["st_np"], ref),
+                                      err_msg=f"request {k}: gathered rows")
+    print(f"{variant}: {len(reqs)} requests, sizes {min(r['w_np'].size for r in reqs)}-"
+          f"{max(r['w_np'].size for r in reqs)}, alone == mixed == oracle")
 
 
 @pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2"])

@@ -1,0 +1,79 @@
+"""The oracle's subset entry point against its full resample.
+
+Parity at large N (the sampled checks at 2^20-2^24, the batch and serving
+tests) compares the HIP path with oracle.resample_subset, which computes
+only the chains of the listed particles. Every chain is independent of the
+others (Algorithms 2-5: particle i's chain reads the weights and its own
+draws only), so the subset must equal the full resample at those indices,
+for every variant, ragged n, step counts across the kernels' 5- and 20-step
+blocks, stream_id != 0, both partition sizes and both Megopolis segment
+widths. Indices are given unsorted and with repeats."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_13504_amd import inputs
+
+VARIANTS = ["metropolis", "c1", "c2", "megopolis"]
+# 1-4: inside the first generator block; 5, 20: block edges; 6, 19, 21, 23,
+# 41: the tails after whole 5- and 20-step blocks
+BS = [1, 4, 5, 6, 19, 20, 21, 23, 41]
+
+
+def _indices(n, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    head = np.arange(min(n, 40))
+    tail = np.arange(max(0, n - 40), n)
+    rnd = g.integers(0, n, size=min(3 * n, 300))
+    idx = np.concatenate([rnd, tail[::-1], head, rnd[:7]]).astype(np.int32)
+    return idx
+
+
+@pytest.mark.parametrize("n", [1, 33, 1000, 4097])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_subset_equals_full_resample(n, variant):
+    w = inputs.gaussian_weights(n, 2.5, 17) if n > 1 else np.array([0.75], dtype=np.float32)
+    idx = _indices(n, 100 + n)
+    for B in BS:
+        for stream_id in (0, 7, 0xFFFFFFFF):
+            seed = 0x1234_5678_9ABC + 31 * B + stream_id
+            full = oracle.resample(w, variant, B, seed, stream_id=stream_id)
+            sub = oracle.resample_subset(w, variant, B, seed, idx, stream_id=stream_id)
+            np.testing.assert_array_equal(sub, full[idx], err_msg=f"{variant} n={n} B={B} sid={stream_id}")
+
+
+@pytest.mark.parametrize("variant", ["c1", "c2"])
+@pytest.mark.parametrize("ps", [8, 128, 2048])
+def test_subset_partition_sizes(variant, ps):
+    n = 4097
+    w = inputs.gaussian_weights(n, 3.0, 5)
+    idx = _indices(n, 9)
+    for B in (6, 21, 60):
+        full = oracle.resample(w, variant, B, 77 + B, stream_id=3, partition_bytes=ps)
+        sub = oracle.resample_subset(w, variant, B, 77 + B, idx, stream_id=3, partition_bytes=ps)
+        np.testing.assert_array_equal(sub, full[idx], err_msg=f"{variant} ps={ps} B={B}")
+
+
+@pytest.mark.parametrize("n", [33, 1000, 4096, 4097])
+def test_subset_segment64_equals_resample_m(n):
+    """With 64-wide segments the subset equals the M = N resample of
+    resample_m (which takes the width), and differs from 32-wide segments
+    once N exceeds 32."""
+    w = inputs.gaussian_weights(n, 2.0, 8)
+    idx = _indices(n, 4)
+    for B in (5, 23, 41):
+        full64 = oracle.resample_m(w, n, "megopolis", B, 900 + B, stream_id=2, segment=64)
+        sub64 = oracle.resample_subset(w, "megopolis", B, 900 + B, idx, stream_id=2, segment=64)
+        np.testing.assert_array_equal(sub64, full64[idx], err_msg=f"n={n} B={B}")
+        full32 = oracle.resample(w, "megopolis", B, 900 + B, stream_id=2)
+        assert not np.array_equal(full64, full32)
+
+
+def test_subset_rejects_bad_input():
+    w = inputs.gaussian_weights(100, 1.0, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.resample_subset(w, "megopolis", 5, 1, [0, 100])
+    with pytest.raises(oracle.OracleError):
+        oracle.resample_subset(w, "megopolis", 5, 1, [-1])
+    with pytest.raises(oracle.OracleError):
+        oracle.resample_subset(w, "megopolis", 5, 1, [3], segment=48)
