@@ -105,6 +105,30 @@ int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes);
 int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
                  mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
 
+/* Bytes of the static scratch that mgp_resample_noalloc uses as its
+ * workspace (64 MiB per device). */
+#define MGP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* mgp_resample without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Same steps, kernels and results as
+ * mgp_resample; the workspace is a fixed array of MGP_NOALLOC_SCRATCH_BYTES
+ * in the library's device memory, one per device, held until the process
+ * ends. The call allocates nothing: on its first call on a device it looks up
+ * that device's copy of the array (hipGetSymbolAddress), with the stream's
+ * device current.
+ * Sizes: mgp_workspace_size(n, params) must fit the scratch, else MGP_ERANGE
+ * and nothing is enqueued. With the default b_max that is n up to about
+ * 8.3 million for MGP_MEGOPOLIS (whose workspace holds the 8n-byte mirror)
+ * and any n for the other variants.
+ * Every call on a device shares that device's scratch and leaves its
+ * contents there: calls that overlap on one device (different streams
+ * without synchronisation) race and must not be issued. The scratch needs
+ * no initialisation. w_dev, ancestors_dev, stats_dev, stream: as
+ * mgp_resample. */
+int mgp_resample_noalloc(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
+                         mgp_stats* stats_dev, void* stream);
+
 /* RESAMPLE with M != N: m ancestors drawn from n weighted inputs, as the
  * paper's closing discussion (Section 8) proposes for D-PMC-style samplers,
  * with the Megopolis offsets ranging over the input count. Output i in

@@ -9,6 +9,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "mgp.h"
 #include "mgp_device.h"
 #include "mgp_internal.h"
@@ -880,6 +882,74 @@ int mgp_resample(const float* w_dev, int32_t n, const mgp_params* params, int32_
     rc = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
     if (rc) return rc;
     return enqueue_resample(w_dev, (uint32_t)n, p, static_cast<char*>(workspace_dev), stats_dev, ancestors_dev,
+                            static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free mgp_resample: the workspace is a fixed array in the code
+// object's device memory instead of a caller buffer. Each device that runs
+// the library holds its own copy of it until the process ends.
+// ---------------------------------------------------------------------------
+static_assert(MGP_NOALLOC_SCRATCH_BYTES % 256 == 0, "the scratch size is a multiple of the workspace alignment");
+static __device__ __align__(256) unsigned char scratch[MGP_NOALLOC_SCRATCH_BYTES];
+
+namespace mgp {
+
+constexpr int kMaxDevices = 64;
+
+// The device address of `scratch` on the current device, looked up once per
+// device (the host-side name of the array is not a device address). Null
+// after a failure, with the error message set.
+static void* scratch_on_current_device(int* rc)
+{
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *rc = fail(MGP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *rc = fail(MGP_EINVAL, "device %d is beyond the %d devices the scratch table covers", dev, kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *rc = fail(MGP_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+            return nullptr;
+        }
+        addr[dev] = p;
+    }
+    *rc = MGP_OK;
+    return addr[dev];
+}
+
+}  // namespace mgp
+
+extern "C" {
+
+int mgp_resample_noalloc(const float* w_dev, int32_t n, const mgp_params* params, int32_t* ancestors_dev,
+                         mgp_stats* stats_dev, void* stream)
+{
+    clear_error();
+    if (!w_dev || !ancestors_dev) return fail(MGP_EINVAL, "w_dev and ancestors_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    Params p;
+    int rc = normalize_params(params, &p);
+    if (rc) return rc;
+    const size_t need = workspace_bytes((uint32_t)n, p);
+    if (need > (size_t)MGP_NOALLOC_SCRATCH_BYTES)
+        return fail(MGP_ERANGE, "n = %d with these params needs %zu bytes of workspace; the static scratch holds %zu",
+                    n, need, (size_t)MGP_NOALLOC_SCRATCH_BYTES);
+    void* ws = scratch_on_current_device(&rc);
+    if (!ws) return rc;
+    return enqueue_resample(w_dev, (uint32_t)n, p, static_cast<char*>(ws), stats_dev, ancestors_dev,
                             static_cast<hipStream_t>(stream));
 }
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libmgp.so")
 
 MGP_OK, MGP_EINVAL, MGP_ERANGE, MGP_ENOMEM, MGP_EHIP, MGP_EBUSY, MGP_EWEIGHTS = 0, -1, -2, -3, -4, -5, -6
 MGP_METROPOLIS, MGP_C1, MGP_C2, MGP_MEGOPOLIS = 0, 1, 2, 3
+MGP_NOALLOC_SCRATCH_BYTES = 64 << 20
 VARIANTS = {"metropolis": MGP_METROPOLIS, "c1": MGP_C1, "c2": MGP_C2, "megopolis": MGP_MEGOPOLIS}
 
 
@@ -131,6 +132,7 @@ def lib():
         L.mgp_resample.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_compute_B.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_resample_m.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, P, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.mgp_resample_noalloc.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, _vp]
         L.mgp_resample_prepared.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_gather.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
         L.mgp_batch_plan_create.argtypes = [ctypes.POINTER(mgp_filter_desc), ctypes.c_int32,
@@ -173,8 +175,8 @@ def lib():
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
         L.mgp_version.argtypes = []
-        for f in ("mgp_workspace_size", "mgp_resample", "mgp_resample_m", "mgp_compute_B", "mgp_resample_prepared", "mgp_gather",
-                  "mgp_version"):
+        for f in ("mgp_workspace_size", "mgp_resample", "mgp_resample_m", "mgp_resample_noalloc", "mgp_compute_B",
+                  "mgp_resample_prepared", "mgp_gather", "mgp_version"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -215,6 +217,12 @@ def mgp_resample(w_dev: int, n: int, params: mgp_params, ancestors_dev: int, sta
                  workspace_bytes: int, stream: int) -> None:
     _check(lib().mgp_resample(w_dev, n, ctypes.byref(params), ancestors_dev, stats_dev or None, workspace_dev,
                               workspace_bytes, stream or None), "mgp_resample")
+
+
+def mgp_resample_noalloc(w_dev: int, n: int, params: mgp_params, ancestors_dev: int, stats_dev: int,
+                         stream: int) -> None:
+    _check(lib().mgp_resample_noalloc(w_dev, n, ctypes.byref(params), ancestors_dev, stats_dev or None,
+                                      stream or None), "mgp_resample_noalloc")
 
 
 def mgp_resample_m(w_dev: int, n: int, m: int, params: mgp_params, ancestors_dev: int, stats_dev: int,

@@ -89,6 +89,21 @@ def test_argument_errors_before_any_device_call(mgp):
     assert e.value.code == mgp.MGP_EINVAL
 
 
+def test_noalloc_size_limit_checked_on_the_host(mgp):
+    """mgp_resample_noalloc rejects a size whose workspace exceeds its static
+    scratch before any device call (the pointers are never dereferenced)."""
+    p = mgp.make_params("megopolis")
+    n = 9_000_000
+    assert mgp.mgp_workspace_size(n, p) > mgp.MGP_NOALLOC_SCRATCH_BYTES
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_resample_noalloc(16, n, p, 16, 0, 0)
+    assert e.value.code == mgp.MGP_ERANGE
+    assert "scratch" in mgp.mgp_last_error()
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_resample_noalloc(0, 100, p, 16, 0, 0)
+    assert e.value.code == mgp.MGP_EINVAL
+
+
 def test_version(mgp):
     assert mgp.mgp_version() >= 100
 
