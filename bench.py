@@ -4,11 +4,12 @@
 A step is one pass of the single-filter path over the N = 2^24 workload
 (Gaussian-likelihood weights, y = 4, eps = 0.01, so B ~ 353), through the
 HIP library's C ABI:
-    mgp_compute_B          reduction (fp32 max, fp64 sum), B, Megopolis offsets
-    mgp_resample_prepared  the accept loop (the dominant kernel)
-    mgp_gather             x_bar_i = x_{k_i}, D = 8 fp32 states
+    mgp_compute_B                 reduction (fp32 max, fp64 sum), B, Megopolis offsets
+    mgp_resample_gather_prepared  the accept loop (the dominant kernel) with
+                                  x_bar_i = x_{k_i} (D = 8 fp32 states) as its epilogue
 Each step uses a new seed. The weights and states are resident in HBM
-before the timed region. Metropolis is timed the same way for comparison.
+before the timed region. Metropolis is timed the same way for comparison,
+and the unfused step (accept loop, then mgp_gather) beside it.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -28,7 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "particles resampled/s at N=2^24 (Megopolis vs Metropolis) + % HBM peak; p99"
 LOOP_SOURCES = ["paper_2109_13504_amd/csrc/mgp_device.h", "paper_2109_13504_amd/csrc/mgp_kernels.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_megopolis_loop_n2pow24_y4.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_megopolis_fused_n2pow24_y4_d8.json")
 
 
 def log(*a):
@@ -72,15 +73,20 @@ def parse():
     ap.add_argument("--sir-bsweep", action="store_true",
                     help="the SIR section for B in {5, 7, 10, 15, 20, 25, 30, 40} and every variant (Section 7's "
                          "B study)")
+    ap.add_argument("--unfused-steps", type=int, default=10,
+                    help="steps of the unfused comparison (accept loop, then mgp_gather)")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the streaming-read ceiling measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 256 MiB (counter calibration for profiling)")
     return ap.parse_args()
 
 
-def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup, seed0, segment=32):
-    """Runs warmup + steps; returns wall ms per step and per-step event times."""
+def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup, seed0, segment=32, fused=True):
+    """Runs warmup + steps; returns wall ms per step and per-step event times.
+    fused: mgp_compute_B, then mgp_resample_gather_prepared (the accept loop
+    with the particle copy as its epilogue); otherwise mgp_compute_B,
+    mgp_resample_prepared and mgp_gather."""
     stream = torch.cuda.current_stream()
-    n = w.numel()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
 
     def one(s, e):
@@ -90,10 +96,15 @@ def timed_steps(torch, mgp, r, w, states, anc, out, variant, eps, steps, warmup,
         r.compute_B(w, variant, epsilon=eps, seed=seed, segment=segment)
         if e:
             e[1].record(stream)
-        r.resample_prepared(w, variant, epsilon=eps, seed=seed, out=anc, segment=segment)
-        if e:
-            e[2].record(stream)
-        mgp.gather(states, anc, out=out)
+        if fused:
+            r.resample_gather_prepared(w, states, variant, epsilon=eps, seed=seed, out=out, anc=anc, segment=segment)
+            if e:
+                e[2].record(stream)
+        else:
+            r.resample_prepared(w, variant, epsilon=eps, seed=seed, out=anc, segment=segment)
+            if e:
+                e[2].record(stream)
+            mgp.gather(states, anc, out=out)
         if e:
             e[3].record(stream)
 
@@ -129,11 +140,14 @@ def cpu_baseline(w_np, variant, eps, stride):
     idx = np.arange(0, n, stride, dtype=np.int32)
     t0 = time.perf_counter()
     B, _, _ = oracle.B_from_weights(w_np, eps)
-    ref = oracle.resample_subset(w_np, variant, B, 12345, idx)
+    ref, accepts = oracle.resample_subset(w_np, variant, B, 12345, idx, return_accepts=True)
     dt = time.perf_counter() - t0
     out = {"value": idx.size / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
            "sample": f"single-threaded C oracle: fp64 reduction + B over all {n} weights, then the B-step chains "
-                     f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s"}
+                     f"of every {stride}th particle ({idx.size} particles, {variant}, B={B}); {dt:.1f} s",
+           # the chains the GPU runs are the same (bit-identical ancestors),
+           # so this is the acceptance rate of the timed accept loop too
+           "acceptance_rate": accepts / (idx.size * B)}
     # the same sample with the chains split over the host's cores (the
     # oracle's calls release the GIL and share no state): identical output
     from concurrent.futures import ThreadPoolExecutor
@@ -148,6 +162,50 @@ def cpu_baseline(w_np, variant, eps, stride):
         if B2 == B and np.array_equal(np.concatenate(got), ref):
             out["all_cores"] = {"value": idx.size / dt2, "cores": threads, "seconds": dt2}
     return out
+
+
+def ceiling_section(torch, mgp):
+    """The memory ceilings the accept loop is compared with, measured here:
+    the streaming-read rate (mgp_probe_stream_read: float4 loads, four in
+    flight per thread, each pass rotated so that the L2 cannot serve a block's
+    next pass) over buffers of 64 MB to 2 GB, each launch reading its buffer
+    as many times as makes about 4 GB; the best of 4096, 8192 and 16384 blocks
+    of 256 threads, median of 3 launches after one warm-up. Up to 256 MB the
+    buffer stays in the 256 MB Infinity Cache (the L2s hold 4 MB per XCD);
+    from 1 GB it streams from HBM."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    buf = torch.ones((2 << 30) // 4, dtype=torch.float32, device=dev)
+    sink = torch.empty(16384, dtype=torch.float32, device=dev)
+    rows = {}
+    for mb in (64, 128, 192, 256, 1024, 2048):
+        nbytes = mb << 20
+        passes = max(1, (4 << 30) // nbytes)
+        best = None
+        for blocks in (4096, 8192, 16384):
+            times = []
+            for k in range(4):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                mgp.mgp_probe_stream_read(buf.data_ptr(), nbytes, passes, blocks, sink.data_ptr(), stream.cuda_stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if k:
+                    times.append(a.elapsed_time(b))
+            ms = float(np.median(times))
+            gbs = passes * nbytes / (ms * 1e-3) / 1e9
+            if best is None or gbs > best["GBs"]:
+                best = {"passes": passes, "blocks": blocks, "ms": ms, "GBs": gbs}
+        rows[f"{mb}MB"] = best
+    del buf, sink
+    mall = max(rows[k]["GBs"] for k in ("64MB", "128MB", "192MB", "256MB"))
+    hbm = max(rows[k]["GBs"] for k in ("1024MB", "2048MB"))
+    log(f"[bench] streaming read: Infinity Cache {mall:.0f} GB/s, HBM {hbm:.0f} GB/s; "
+        + ", ".join(f"{k} {v['GBs']:.0f}" for k, v in rows.items()))
+    return {"workload": "streaming read (mgp_probe_stream_read), ~4 GB per launch, best of 4096/8192/16384 blocks "
+                        "x 256 threads, median of 3", "rows": rows, "infinity_cache_read_GBs": mall,
+            "hbm_read_GBs": hbm}
 
 
 def batched_section(torch, mgp, inputs, runs, shape=None):
@@ -595,11 +653,29 @@ def main():
     st = r.last_stats()
     B = st["B"]
     assert st["status"] == 0
-    loop_ms = float(np.mean(per["loop"]))
-    loop_bytes = 4.0 * n * (B + 2)  # B candidate weights + own weight + ancestor write, per particle
-    achieved = loop_bytes / (loop_ms * 1e-3) / 1e9
-    step_bytes = 4.0 * n + 4.0 * n * (B + 2) + 4.0 * n * (2 * args.d + 1)
-    log(f"[bench] {args.variant}: {ms:.3f} ms/step, loop {loop_ms:.3f} ms, B={B}, {achieved:.0f} GB/s effective")
+    d = args.d
+    fused_ms = float(np.mean(per["loop"]))
+    # what the fused kernel must move per launch: B candidate weights, the
+    # particle's own weight, the ancestor write, and the state row read and
+    # written (the gather's ancestor re-read is gone)
+    fused_bytes = 4.0 * n * B + 4.0 * n + 4.0 * n + 8.0 * n * d
+    achieved = fused_bytes / (fused_ms * 1e-3) / 1e9
+    step_bytes = 4.0 * n + fused_bytes
+    log(f"[bench] {args.variant}: {ms:.3f} ms/step, loop + copy {fused_ms:.3f} ms, B={B}, {achieved:.0f} GB/s")
+
+    # the same step unfused (accept loop, then mgp_gather), for the loop-only
+    # rate of 4 N B weight bytes and the saving of the fusion
+    ms_u, per_u = timed_steps(torch, mgp, r, w, states, anc, out, args.variant, args.eps, max(1, args.unfused_steps),
+                              1, 500, fused=False)
+    loop_ms = float(np.mean(per_u["loop"]))
+    loop_bytes = 4.0 * n * B
+    log(f"[bench] unfused: {ms_u:.3f} ms/step, loop {loop_ms:.3f} ms, gather {float(np.mean(per_u['gather'])):.3f} ms")
+
+    ceil = None if args.no_ceiling else ceiling_section(torch, mgp)
+    mall = ceil["infinity_cache_read_GBs"] if ceil else float("nan")
+    hbm = ceil["hbm_read_GBs"] if ceil else float("nan")
+    kernel = {"megopolis": f"k_megopolis_mirror<4, {d // 4 if d % 4 == 0 and d <= 16 else -1}>",
+              }.get(args.variant, f"k_resample<{args.variant}>")
 
     result = {
         "metric": METRIC,
@@ -615,31 +691,51 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"single filter, N=2^{args.log2n}, Gaussian-likelihood weights y={args.y:g}, "
-                               f"eps={args.eps:g} (B={B}), {args.variant}, gather of D={args.d} fp32 states",
-                   "n": n, "y": args.y, "eps": args.eps, "B": B, "d": args.d, "variant": args.variant,
-                   "step": "compute_B + accept loop + gather"},
+                               f"eps={args.eps:g} (B={B}), {args.variant}, with the particle copy of D={d} fp32 "
+                               f"states fused into the accept loop",
+                   "n": n, "y": args.y, "eps": args.eps, "B": B, "d": d, "variant": args.variant,
+                   "step": "mgp_compute_B + mgp_resample_gather_prepared"},
         "p50_ms": pct(per["total"], 50),
         "p99_ms": pct(per["total"], 99),
-        "phase_ms": {k: float(np.mean(v)) for k, v in per.items()},
+        "phase_ms": {"reduce_B": float(np.mean(per["reduce_B"])), "loop_and_copy": fused_ms,
+                     "total": float(np.mean(per["total"]))},
         "hbm_frac_effective": (step_bytes / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
         "roofline": {
-            "kernel": "k_megopolis_mirror<4> (accept loop)" if args.variant == "megopolis" else
-                      f"k_resample<{args.variant}> (accept loop)",
+            "kernel": f"{kernel} (accept loop with the particle copy as its epilogue)",
             "bound": "hbm",
+            "level": "memory side of the fabric: the 128 MB weight mirror streams from the 256 MB Infinity Cache "
+                     "in front of HBM; the state rows come from and go to HBM",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "algorithmic_bytes_per_launch": loop_bytes,
-            "avg_launch_ms": loop_ms,
+            "bytes_formula": "4NB candidate weights + 4N own weight + 4N ancestor + 8ND state row in and out",
+            "algorithmic_bytes_per_launch": fused_bytes,
+            "avg_launch_ms": fused_ms,
+            "ceiling": {"infinity_cache_read_GBs": mall, "frac_of_infinity_cache_read": achieved / mall,
+                        "hbm_read_GBs": hbm,
+                        "what": "mgp_probe_stream_read in this run: the best streaming-read rate over buffers of "
+                                "64-256 MB (Infinity Cache resident) and at 1-2 GB (HBM)"},
             "traffic": None,
+            "traffic_what": "bytes past the L2 (TCC to fabric: Infinity Cache or HBM), calibrated FETCH_SIZE + "
+                            "WRITE_SIZE per launch",
         },
+        "loop_only": {"kernel": "k_megopolis_mirror<4, 0> (accept loop, unfused step)" if args.variant == "megopolis"
+                      else f"k_resample<{args.variant}>",
+                      "ms": loop_ms, "bytes_formula": "4NB candidate weights", "bytes": loop_bytes,
+                      "GBs": loop_bytes / (loop_ms * 1e-3) / 1e9,
+                      "frac_of_hbm_peak": loop_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "frac_of_infinity_cache_read": loop_bytes / (loop_ms * 1e-3) / 1e9 / mall},
+        "unfused": {"ms_per_step": ms_u, "loop_ms": loop_ms, "gather_ms": float(np.mean(per_u["gather"])),
+                    "gather_GBs": 4.0 * n * (2 * d + 1) / (float(np.mean(per_u["gather"])) * 1e-3) / 1e9,
+                    "fused_saving_ms": ms_u - ms},
+        "memory_ceilings": ceil,
     }
 
     if os.path.exists(TRAFFIC_FILE):
         t = json.load(open(TRAFFIC_FILE))
-        if t.get("source_hash") == source_hash() and t.get("n") == n and t.get("B") == B:
-            result["roofline"]["traffic"] = t["hbm_bytes_per_launch"]
+        if t.get("source_hash") == source_hash() and t.get("n") == n and t.get("B") == B and t.get("d") == d:
+            result["roofline"]["traffic"] = t["bytes_per_launch"]
 
     if not args.no_metropolis and args.variant != "metropolis":
         log(f"[bench] metropolis: {args.metropolis_steps} steps")
@@ -647,16 +743,18 @@ def main():
                                   args.metropolis_steps, 1, 0)
         lm = float(np.mean(per_m["loop"]))
         result["metropolis"] = {"value": n / (ms_m * 1e-3), "unit": "particles/s", "ms_per_step": ms_m,
-                                "loop_ms": lm, "effective_GBs": loop_bytes / (lm * 1e-3) / 1e9,
-                                "p99_ms": pct(per_m["total"], 99)}
+                                "loop_and_copy_ms": lm,
+                                "effective_GBs": fused_bytes / (lm * 1e-3) / 1e9,
+                                "p99_ms": pct(per_m["total"], 99),
+                                "step": "mgp_compute_B + mgp_resample_gather_prepared, as for Megopolis"}
         result["speedup_vs_metropolis"] = ms_m / ms
-        log(f"[bench] metropolis: {ms_m:.3f} ms/step, loop {lm:.3f} ms -> speedup {ms_m / ms:.2f}x")
+        log(f"[bench] metropolis: {ms_m:.3f} ms/step, loop + copy {lm:.3f} ms -> speedup {ms_m / ms:.2f}x")
 
     if args.variant == "megopolis" and not args.no_segment64:
         ms_s, per_s = timed_steps(torch, mgp, r, w, states, anc, out, "megopolis", args.eps, 5, 1, 0, segment=64)
         ls = float(np.mean(per_s["loop"]))
-        result["megopolis_segment64"] = {"ms_per_step": ms_s, "loop_ms": ls,
-                                         "effective_GBs": loop_bytes / (ls * 1e-3) / 1e9,
+        result["megopolis_segment64"] = {"ms_per_step": ms_s, "loop_and_copy_ms": ls,
+                                         "effective_GBs": fused_bytes / (ls * 1e-3) / 1e9,
                                          "workload": "the same step with 64-wide Megopolis segments"}
         log(f"[bench] megopolis, 64-wide segments: {ms_s:.3f} ms/step, loop {ls:.3f} ms")
 

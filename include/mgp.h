@@ -170,6 +170,31 @@ int mgp_resample_prepared(const float* w_dev, int32_t n, const mgp_params* param
 int mgp_gather(const float* states_dev, int32_t n_states, int32_t d, const int32_t* ancestors_dev,
                int32_t n_out, float* out_dev, void* stream);
 
+/* RESAMPLE(x, w) -> x_bar in one pass: mgp_resample with the particle copy
+ * x_bar_i = x_{k_i} that ends Algorithms 2-5 done by the accept loop itself,
+ * while each ancestor k_i is still in a register (no second launch, no
+ * re-read of the ancestor array).
+ * states_dev    : n x d fp32, row-major, device (the particles x).
+ * d             : floats per row, >= 1 (d % 4 == 0 with 16-byte aligned
+ *                 states_dev and out_dev moves float4s).
+ * out_dev       : n x d fp32, device, written (x_bar); must not overlap
+ *                 states_dev.
+ * ancestors_dev : n int32, device, written; NULL when only x_bar is wanted.
+ * w_dev, params, stats_dev, workspace: as mgp_resample (same steps, same
+ * launch counts). The result equals mgp_resample followed by mgp_gather on
+ * the same arguments, bit for bit; invalid weights give -1 ancestors and NaN
+ * rows. */
+int mgp_resample_gather(const float* w_dev, int32_t n, const mgp_params* params, const float* states_dev, int32_t d,
+                        int32_t* ancestors_dev, float* out_dev, mgp_stats* stats_dev, void* workspace_dev,
+                        size_t workspace_bytes, void* stream);
+
+/* Step 3 of mgp_resample_gather only (the accept loop with the particle
+ * copy), after mgp_compute_B on this workspace: as mgp_resample_prepared,
+ * with states_dev, d, ancestors_dev and out_dev as in mgp_resample_gather. */
+int mgp_resample_gather_prepared(const float* w_dev, int32_t n, const mgp_params* params, const float* states_dev,
+                                 int32_t d, int32_t* ancestors_dev, float* out_dev, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream);
+
 /* ---- batched filters ----------------------------------------------------
  * Many independent filters of uneven size resampled by one graph launch.
  * Each filter's result is exactly that of mgp_resample (+ mgp_gather) with
@@ -455,6 +480,21 @@ const char* mgp_last_error(void);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int mgp_version(void);
+
+/* ---- memory-system probe -------------------------------------------------
+ * The streaming-read rate of the device at one buffer size: the benchmark
+ * reports it as the memory ceiling beside the accept loop's achieved rate
+ * (the loop streams its mirrored weights from whichever level holds them).
+ * One launch of `blocks` blocks of 256 threads reads every 16-byte vector of
+ * buf_dev[0, bytes) `passes` times (grid-stride, four loads in flight per
+ * thread; each pass starts its sweep about 38% of the buffer further on, so
+ * a block's reads are not served by the L2 its previous pass filled) and
+ * writes one float per block to sink_dev (blocks floats, device), so no load
+ * is elided. bytes: a positive multiple of 16, below 16 GiB (MGP_ERANGE);
+ * buf_dev 16-byte aligned; contents are read, never written. Time it with
+ * events on `stream`: rate = passes * bytes / time. */
+int mgp_probe_stream_read(const void* buf_dev, size_t bytes, int32_t passes, int32_t blocks, float* sink_dev,
+                          void* stream);
 
 #ifdef __cplusplus
 }

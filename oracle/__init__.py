@@ -76,7 +76,8 @@ def lib():
         L.mgp_oracle_resample_m.restype = ctypes.c_int
         L.mgp_oracle_resample_subset.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
                                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
-                                                 _u32p, _i32p, ctypes.c_int32, _i32p]
+                                                 _u32p, _i32p, ctypes.c_int32, _i32p,
+                                                 ctypes.POINTER(ctypes.c_uint64)]
         L.mgp_oracle_resample_subset.restype = ctypes.c_int
         L.mgp_oracle_trace.argtypes = [ctypes.c_int32, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
                                        ctypes.c_uint32, ctypes.c_uint32, _u32p, ctypes.c_int32, _u32p, _f32p]
@@ -205,18 +206,22 @@ def resample_m(w: np.ndarray, m: int, variant, B: int, seed: int, stream_id: int
 
 
 def resample_subset(w: np.ndarray, variant, B: int, seed: int, idx, stream_id: int = 0,
-                    partition_bytes: int = 128, segment: int = 32) -> np.ndarray:
+                    partition_bytes: int = 128, segment: int = 32, return_accepts: bool = False):
     """Ancestors of the particles idx only (the chains of resample(), each
-    computed alone); `segment` is the Megopolis segment width, 32 or 64."""
+    computed alone); `segment` is the Megopolis segment width, 32 or 64.
+    With return_accepts, also the number of accepted steps of these chains."""
     w = np.ascontiguousarray(w, dtype=np.float32)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     out = np.empty(idx.size, dtype=np.int32)
     scratch = np.zeros(max(B, 1), dtype=np.uint32)
+    acc = ctypes.c_uint64()
     rc = lib().mgp_oracle_resample_subset(_ptr(w, _f32p), w.size, _variant(variant), B, seed, stream_id,
                                           partition_bytes, segment, _ptr(scratch, _u32p), _ptr(idx, _i32p), idx.size,
-                                          _ptr(out, _i32p))
+                                          _ptr(out, _i32p), ctypes.byref(acc))
     if rc:
         raise OracleError(rc, "mgp_oracle_resample_subset")
+    if return_accepts:
+        return out, int(acc.value)
     return out
 
 

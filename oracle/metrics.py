@@ -40,6 +40,7 @@ class QualityAccumulator:
         self.se_sum = 0.0
         self.o_sum = np.zeros(self.n, dtype=np.float64)
         self.se_list = []
+        self.o_sq_sum = np.zeros(self.n, dtype=np.float64)
 
     def add(self, anc: np.ndarray) -> None:
         o = offspring(anc, self.n).astype(np.float64)
@@ -48,7 +49,22 @@ class QualityAccumulator:
         self.se_sum += se
         self.se_list.append(se)
         self.o_sum += o
+        self.o_sq_sum += o * o
         self.k += 1
+
+    def mean_offspring(self) -> np.ndarray:
+        return self.o_sum / self.k
+
+    def variance_sum(self) -> float:
+        """sum_i of the sample variance of o^(i) over the K vectors (1/(K-1))."""
+        m = self.o_sum / self.k
+        return float(np.sum((self.o_sq_sum - self.k * m * m) / (self.k - 1)))
+
+    def bias_sq_debiased(self) -> float:
+        """||Bias||^2 less the part that the finite K adds to it: the squared
+        distance of the K-sample mean from the expected offspring exceeds the
+        squared bias by (sum_i Var o^(i)) / K on average."""
+        return self.bias_sq() - self.variance_sum() / self.k
 
     def mse(self) -> float:
         return self.se_sum / self.k

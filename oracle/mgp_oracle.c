@@ -288,11 +288,12 @@ int mgp_oracle_resample_m(const float* w, int32_t n, int32_t m, int variant, uin
 
 /* Ancestors of the particles idx[0..count) only: the same chains as
  * mgp_oracle_resample (each chain is independent of the others), with the
- * Megopolis segment width `segment` (32, the paper's, or 64). */
+ * Megopolis segment width `segment` (32, the paper's, or 64). When accepts
+ * is not NULL it receives the number of accepted steps of these chains. */
 int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t B, uint64_t seed,
                                uint32_t stream_id, uint32_t partition_bytes, uint32_t segment,
                                uint32_t* offsets_scratch, const int32_t* idx, int32_t count,
-                               int32_t* ancestors)
+                               int32_t* ancestors, uint64_t* accepts)
 {
     int rc = check_common(variant, n, partition_bytes);
     if (rc) return rc;
@@ -302,10 +303,11 @@ int mgp_oracle_resample_subset(const float* w, int32_t n, int variant, uint32_t 
         mgp_oracle_offsets(seed, stream_id, (uint32_t)n, B, offsets_scratch);
     }
     uint32_t n_w = partition_bytes / 4u;
+    if (accepts) *accepts = 0;
     for (int32_t c = 0; c < count; ++c) {
         if (idx[c] < 0 || idx[c] >= n) return OR_EINVAL;
         ancestors[c] = run_chain(w, (uint32_t)n, variant, B, seed, stream_id, n_w, segment,
-                                 offsets_scratch, (uint32_t)idx[c], (uint32_t)idx[c], NULL);
+                                 offsets_scratch, (uint32_t)idx[c], (uint32_t)idx[c], accepts);
     }
     return OR_OK;
 }

@@ -22,6 +22,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace mgp {
@@ -452,6 +453,78 @@ __device__ __forceinline__ uint32_t megopolis_mirror_chain_deep(const char* __re
     }
     const uint32_t k = kk / 4u;
     return k >= n ? k - n : k;
+}
+
+// ---------------------------------------------------------------------------
+// The particle copy that closes Algorithms 2-5, x_bar_i = x_{k_i}: rows of d
+// fp32 states, row-major, streamed to the output past the L2 (written once,
+// never read here). The accept loops run it as an epilogue while the
+// ancestors are still in registers; the stand-alone gather runs it over an
+// ancestor array. A negative ancestor (invalid weights) gives a NaN row.
+// ---------------------------------------------------------------------------
+struct RowCopy {
+    const float* states;  // input rows; null: nothing is copied
+    float* out;           // one row per output particle
+    uint32_t d;           // floats per row
+    uint32_t vec4;        // d % 4 == 0 and both buffers 16-byte aligned: float4 moves
+};
+
+__device__ __forceinline__ void store_stream(float4* p, const float4& v)
+{
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z);
+    __builtin_nontemporal_store(v.w, &p->w);
+}
+
+// Output row i from input row k, one lane, any d.
+__device__ __forceinline__ void copy_row(const RowCopy& g, uint32_t i, int32_t k)
+{
+    const float4 nan4 = make_float4(NAN, NAN, NAN, NAN);
+    const uint64_t kr = k < 0 ? 0u : (uint64_t)k;
+    if (g.vec4) {
+        const uint32_t d4 = g.d >> 2;
+        const float4* src = reinterpret_cast<const float4*>(g.states) + kr * d4;
+        float4* dst = reinterpret_cast<float4*>(g.out) + (uint64_t)i * d4;
+        uint32_t c = 0;
+        for (; c + 4u <= d4; c += 4u) {  // four loads in flight before the stores
+            float4 v[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u) v[u] = k < 0 ? nan4 : src[c + u];
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u) store_stream(dst + c + u, v[u]);
+        }
+        for (; c < d4; ++c) store_stream(dst + c, k < 0 ? nan4 : src[c]);
+    } else {
+        const float* src = g.states + kr * g.d;
+        float* dst = g.out + (uint64_t)i * g.d;
+        for (uint32_t c = 0; c < g.d; ++c) __builtin_nontemporal_store(k < 0 ? NAN : src[c], dst + c);
+    }
+}
+
+// The rows of P outputs of one lane with D4 float4s per row known at compile
+// time (g.vec4 set): every load of the P rows is issued before the first
+// store. Outputs with live[p] false are skipped.
+template <int P, int D4>
+__device__ __forceinline__ void copy_rows_vec4(const RowCopy& g, const uint32_t (&i)[P], const int32_t (&k)[P],
+                                               const bool (&live)[P])
+{
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(g.states);
+    float4* __restrict__ dst = reinterpret_cast<float4*>(g.out);
+    float4 v[P][D4];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint64_t kr = k[p] < 0 ? 0u : (uint64_t)k[p];
+#pragma unroll
+        for (int c = 0; c < D4; ++c)
+            if (live[p]) v[p][c] = k[p] < 0 ? make_float4(NAN, NAN, NAN, NAN) : src[kr * D4 + c];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int c = 0; c < D4; ++c)
+            if (live[p]) store_stream(dst + (uint64_t)i[p] * D4 + c, v[p][c]);
+    }
 }
 
 }  // namespace mgp

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "mgp.h"
+#include "mgp_device.h"
 
 namespace mgp {
 
@@ -79,10 +80,14 @@ uint32_t reduce_blocks(uint32_t n);
 uint32_t reduce_chunk(uint32_t n, uint32_t blocks);
 int enqueue_reduce_finalize(const float* w, uint32_t n, const Params& p, bool make_offsets, char* ws,
                             mgp_stats* st_user, hipStream_t stream);
-int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream);
+// The accept loop (after the reduction and finalize launches); with rc.states
+// set, the particle copy x_bar_i = x_{k_i} runs as its epilogue. anc may be
+// null when rc copies the rows.
+int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream,
+                 const RowCopy& rc = RowCopy{});
 // The accept loop for m outputs drawn from n weighted inputs (M != N).
 int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char* ws, int32_t* anc,
-                   hipStream_t stream);
+                   hipStream_t stream, const RowCopy& rc = RowCopy{});
 int enqueue_gather(const float* states, uint32_t n_states, uint32_t d, const int32_t* anc, uint32_t n_out,
                    float* out, hipStream_t stream);
 // mgp_resample's work: one launch up to 8192 (Megopolis) or 4096 particles,
@@ -90,6 +95,6 @@ int enqueue_gather(const float* states, uint32_t n_states, uint32_t d, const int
 // leaving nothing in the workspace for a prepared loop; else the reduction +
 // finalize and the accept loop.
 int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
-                     hipStream_t stream);
+                     hipStream_t stream, const RowCopy& rc = RowCopy{});
 
 }  // namespace mgp

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
                                                            const uint32_t* __restrict__ offsets, uint32_t key0,
                                                            uint32_t key1, uint32_t stream_id, uint32_t n_w,
                                                            uint32_t n_part, uint32_t tag, uint32_t b_cap,
-                                                           uint32_t seg_mask, int32_t* __restrict__ anc)
+                                                           uint32_t seg_mask, int32_t* __restrict__ anc, RowCopy rc)
 {
     const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
     const uint32_t B = st->B;
@@ -97,42 +97,61 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
     // variant, seed and stream), and B must fit the workspace
     const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
     if (i >= m) return;
-    if (!ok) {
-        anc[i] = -1;
-        return;
+    int32_t k = -1;
+    if (ok) {
+        LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part, seg_mask};
+        // output i starts at input i mod n (i itself when m <= n)
+        const uint32_t pos = i < n ? i : i % n;
+        k = (int32_t)run_chain<V, Narrow>(P, i, pos);
     }
-    LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part, seg_mask};
-    // output i starts at input i mod n (i itself when m <= n)
-    const uint32_t pos = i < n ? i : i % n;
-    anc[i] = (int32_t)run_chain<V, Narrow>(P, i, pos);
+    if (anc) anc[i] = k;
+    if (rc.states) copy_row(rc, i, k);
 }
 
 // Megopolis over the mirrored weights, kMegopolisPPT particles per thread.
-template <int P>
+// Rows selects the particle copy of the epilogue: 0 none, D4 > 0 rows of D4
+// float4s, -1 any row shape (copy_row).
+template <int P, int Rows>
 __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror(const float* __restrict__ mirror, uint32_t n,
                                                                    uint32_t m, const mgp_stats* __restrict__ st,
                                                                    const uint32_t* __restrict__ offsets,
                                                                    uint32_t key0, uint32_t key1, uint32_t stream_id,
                                                                    uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
-                                                                   int32_t* __restrict__ anc)
+                                                                   int32_t* __restrict__ anc, RowCopy rc)
 {
     const uint32_t i0 = blockIdx.x * (kLoopThreads * P) + threadIdx.x;
     const uint32_t B = st->B;
     const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
-    if (!ok) {
+    uint32_t idx[P];
+    int32_t k[P];
+    bool live[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        idx[p] = i0 + kLoopThreads * p;
+        live[p] = idx[p] < m;
+        k[p] = -1;
+    }
+    if (ok) {
+        // every lane runs, also past m (m <= n here): the mirror's padding
+        // keeps those loads in bounds, and only real outputs store
+        uint32_t kc[P];
+        megopolis_mirror_chain<P>(reinterpret_cast<const char*>(mirror), offsets, n, B, key0, key1, stream_id, i0,
+                                  kc, seg_mask);
+#pragma unroll
+        for (int p = 0; p < P; ++p) k[p] = (int32_t)kc[p];
+    }
+    if (anc) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
-            if (i0 + kLoopThreads * p < m) anc[i0 + kLoopThreads * p] = -1;
-        return;
+            if (live[p]) anc[idx[p]] = k[p];
     }
-    // every lane runs, also past m (m <= n here): the mirror's padding keeps
-    // those loads in bounds, and only real outputs store
-    uint32_t k[P];
-    megopolis_mirror_chain<P>(reinterpret_cast<const char*>(mirror), offsets, n, B, key0, key1, stream_id, i0, k,
-                              seg_mask);
+    if constexpr (Rows > 0) {
+        copy_rows_vec4<P, Rows>(rc, idx, k, live);
+    } else if constexpr (Rows < 0) {
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-        if (i0 + kLoopThreads * p < m) anc[i0 + kLoopThreads * p] = (int32_t)k[p];
+        for (int p = 0; p < P; ++p)
+            if (live[p]) copy_row(rc, idx[p], k[p]);
+    }
 }
 
 // Megopolis over the mirrored weights for small n: one particle per thread,
@@ -148,19 +167,20 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_mirror_deep(const fl
                                                                         uint32_t key0, uint32_t key1,
                                                                         uint32_t stream_id, uint32_t tag,
                                                                         uint32_t b_cap, uint32_t seg_mask,
-                                                                        int32_t* __restrict__ anc)
+                                                                        int32_t* __restrict__ anc, RowCopy rc)
 {
     const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
     const uint32_t B = st->B;
     const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
-    if (!ok) {
-        if (i < m) anc[i] = -1;
-        return;
-    }
+    int32_t k = -1;
     // lanes past m run too (the mirror's padding keeps their loads in bounds)
-    const uint32_t k = megopolis_mirror_chain_deep<kDeepSteps>(reinterpret_cast<const char*>(mirror), offsets, n, B,
-                                                               key0, key1, stream_id, i, seg_mask);
-    if (i < m) anc[i] = (int32_t)k;
+    if (ok)
+        k = (int32_t)megopolis_mirror_chain_deep<kDeepSteps>(reinterpret_cast<const char*>(mirror), offsets, n, B,
+                                                             key0, key1, stream_id, i, seg_mask);
+    if (i < m) {
+        if (anc) anc[i] = k;
+        if (rc.states) copy_row(rc, i, k);
+    }
 }
 
 
@@ -310,7 +330,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
                                                                   const uint32_t* __restrict__ offsets,
                                                                   uint32_t key0, uint32_t key1, uint32_t stream_id,
                                                                   uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
-                                                                  int32_t* __restrict__ anc, SplitArgs f)
+                                                                  int32_t* __restrict__ anc, SplitArgs f, RowCopy rc)
 {
     __shared__ float su[kSplitPass + 1][64];   // row kSplitPass: the spare row
     __shared__ float swj[kSplitPass + 1][64];
@@ -351,7 +371,10 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
         ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
     }
     if (!ok) {
-        if (q == 0 && i < m) anc[i] = -1;
+        if (q == 0 && i < m) {
+            if (anc) anc[i] = -1;
+            if (rc.states) copy_row(rc, i, -1);
+        }
         return;
     }
     // lanes past m run too (the mirror's padding keeps their loads in bounds)
@@ -448,7 +471,9 @@ __global__ __launch_bounds__(kLoopThreads) void k_megopolis_split(const float* _
     }
     if (q == 0 && i < m) {
         const uint32_t k = kk / 4u;
-        anc[i] = (int32_t)(k >= n ? k - n : k);
+        const int32_t kn = (int32_t)(k >= n ? k - n : k);
+        if (anc) anc[i] = kn;
+        if (rc.states) copy_row(rc, i, kn);
     }
 }
 
@@ -462,7 +487,8 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample_small(const float* __
                                                                  uint32_t fold_vec, FinalizeArgs a,
                                                                  mgp_stats* __restrict__ st_ws,
                                                                  mgp_stats* __restrict__ st_user, uint32_t n_w,
-                                                                 uint32_t n_part, int32_t* __restrict__ anc)
+                                                                 uint32_t n_part, int32_t* __restrict__ anc,
+                                                                 RowCopy rc)
 {
     __shared__ __align__(16) float M[2 * kSmallMaxN + kSmallPad];
     __shared__ Partial parts[kSmallMaxParts];
@@ -470,12 +496,13 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample_small(const float* __
     const uint32_t B = small_prologue(w, n, nparts, chunk, copy_vec, fold_vec, a, st_ws, st_user, M, parts, &st_local);
     const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
     if (i >= n) return;
-    if (B == 0) {  // invalid weights
-        anc[i] = -1;
-        return;
+    int32_t k = -1;  // invalid weights: B == 0
+    if (B > 0) {
+        const LoopParams P{M, nullptr, n, B, a.key0, a.key1, a.stream_id, n_w, n_part};
+        k = (int32_t)run_chain<V, true>(P, i, i);
     }
-    const LoopParams P{M, nullptr, n, B, a.key0, a.key1, a.stream_id, n_w, n_part};
-    anc[i] = (int32_t)run_chain<V, true>(P, i, i);
+    if (anc) anc[i] = k;
+    if (rc.states) copy_row(rc, i, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,23 +662,34 @@ template <int V>
 static void launch_loop(bool narrow, dim3 grid, hipStream_t s, const float* w, uint32_t n, uint32_t m,
                         const mgp_stats* st, const uint32_t* offs, uint32_t k0, uint32_t k1, uint32_t sid,
                         uint32_t n_w, uint32_t n_part, uint32_t tag, uint32_t b_cap, uint32_t seg_mask,
-                        int32_t* anc)
+                        int32_t* anc, const RowCopy& rc)
 {
     if (narrow)
         hipLaunchKernelGGL((k_resample<V, true>), grid, dim3(kLoopThreads), 0, s, w, n, m, st, offs, k0, k1, sid,
-                           n_w, n_part, tag, b_cap, seg_mask, anc);
+                           n_w, n_part, tag, b_cap, seg_mask, anc, rc);
     else
         hipLaunchKernelGGL((k_resample<V, false>), grid, dim3(kLoopThreads), 0, s, w, n, m, st, offs, k0, k1, sid,
-                           n_w, n_part, tag, b_cap, seg_mask, anc);
+                           n_w, n_part, tag, b_cap, seg_mask, anc, rc);
 }
 
-int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream)
+// The four-particle Megopolis loop with the epilogue that fits the row copy.
+template <int Rows>
+static void launch_mirror(dim3 g, hipStream_t s, const float* mirror, uint32_t n, uint32_t m, const mgp_stats* st,
+                          const uint32_t* offs, uint32_t k0, uint32_t k1, uint32_t sid, uint32_t tag, uint32_t cap,
+                          uint32_t seg_mask, int32_t* anc, const RowCopy& rc)
 {
-    return enqueue_loop_m(w, n, n, p, ws, anc, stream);
+    hipLaunchKernelGGL((k_megopolis_mirror<kMegopolisPPT, Rows>), g, dim3(kLoopThreads), 0, s, mirror, n, m, st, offs,
+                       k0, k1, sid, tag, cap, seg_mask, anc, rc);
+}
+
+int enqueue_loop(const float* w, uint32_t n, const Params& p, char* ws, int32_t* anc, hipStream_t stream,
+                 const RowCopy& rc)
+{
+    return enqueue_loop_m(w, n, n, p, ws, anc, stream, rc);
 }
 
 int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char* ws, int32_t* anc,
-                   hipStream_t stream)
+                   hipStream_t stream, const RowCopy& rc)
 {
     const mgp_stats* st = reinterpret_cast<const mgp_stats*>(ws + kWsStatsOffset);
     const uint32_t* offs = reinterpret_cast<const uint32_t*>(ws + kWsOffsetsOffset);
@@ -670,10 +708,10 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
         if (m <= kSplitMaxM) {
             hipLaunchKernelGGL(k_megopolis_split<kSplitPrepared>, dim3((m + 63u) / 64u), dim3(kLoopThreads), 0, stream,
-                               mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, SplitArgs{});
+                               mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, SplitArgs{}, rc);
         } else {
             hipLaunchKernelGGL(k_megopolis_mirror_deep, grid, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs,
-                               k0, k1, p.stream_id, tag, cap, seg_mask, anc);
+                               k0, k1, p.stream_id, tag, cap, seg_mask, anc, rc);
         }
         return check_launch("megopolis kernel (small n)");
     }
@@ -681,22 +719,35 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
         constexpr int P = kMegopolisPPT;
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
         const dim3 g((m + kLoopThreads * P - 1u) / (kLoopThreads * P));
-        hipLaunchKernelGGL((k_megopolis_mirror<P>), g, dim3(kLoopThreads), 0, stream, mirror, n, m, st, offs, k0, k1,
-                           p.stream_id, tag, cap, seg_mask, anc);
+        const uint32_t d4 = rc.vec4 ? rc.d / 4u : 0u;
+        if (!rc.states)
+            launch_mirror<0>(g, stream, mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, rc);
+        else if (d4 == 1u)
+            launch_mirror<1>(g, stream, mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, rc);
+        else if (d4 == 2u)
+            launch_mirror<2>(g, stream, mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, rc);
+        else if (d4 == 4u)
+            launch_mirror<4>(g, stream, mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, rc);
+        else
+            launch_mirror<-1>(g, stream, mirror, n, m, st, offs, k0, k1, p.stream_id, tag, cap, seg_mask, anc, rc);
         return check_launch("megopolis kernel");
     }
     switch (p.variant) {
     case kMetropolis:
-        launch_loop<kMetropolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
+        launch_loop<kMetropolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc,
+                         rc);
         break;
     case kC1:
-        launch_loop<kC1>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
+        launch_loop<kC1>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc,
+                         rc);
         break;
     case kC2:
-        launch_loop<kC2>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
+        launch_loop<kC2>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc,
+                         rc);
         break;
     default:
-        launch_loop<kMegopolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc);
+        launch_loop<kMegopolis>(narrow, grid, stream, w, n, m, st, offs, k0, k1, p.stream_id, n_w, n_part, tag, cap, seg_mask, anc,
+                         rc);
         break;
     }
     return check_launch("resample kernel");
@@ -708,7 +759,7 @@ int enqueue_loop_m(const float* w, uint32_t n, uint32_t m, const Params& p, char
 // uses for the same n, variant and weight alignment (float4 folds need a
 // 16-byte aligned w, and with a mirror n % 4 == 0).
 int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
-                  hipStream_t stream)
+                  hipStream_t stream, const RowCopy& rc)
 {
     const uint32_t g = reduce_blocks(n);
     const uint32_t chunk = reduce_chunk(n, g);
@@ -733,36 +784,36 @@ int enqueue_small(const float* w, uint32_t n, const Params& p, char* ws, mgp_sta
             f.fold_vec = copy_vec;
             hipLaunchKernelGGL(k_megopolis_split<kSplitSmall>, dim3((n + 63u) / 64u), dim3(kLoopThreads), 0, stream,
                                nullptr, n, n, nullptr, nullptr, a.key0, a.key1, p.stream_id, a.tag, p.b_max,
-                               p.segment - 1u, anc, f);
+                               p.segment - 1u, anc, f, rc);
             break;
         }
     case kMetropolis:
         hipLaunchKernelGGL(k_resample_small<kMetropolis>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk,
-                           copy_vec, fold_vec, a, st_ws, st_user, n_w, n_part, anc);
+                           copy_vec, fold_vec, a, st_ws, st_user, n_w, n_part, anc, rc);
         break;
     case kC1:
         hipLaunchKernelGGL(k_resample_small<kC1>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, copy_vec,
-                           fold_vec, a, st_ws, st_user, n_w, n_part, anc);
+                           fold_vec, a, st_ws, st_user, n_w, n_part, anc, rc);
         break;
     default:
         hipLaunchKernelGGL(k_resample_small<kC2>, grid, dim3(kLoopThreads), 0, stream, w, n, g, chunk, copy_vec,
-                           fold_vec, a, st_ws, st_user, n_w, n_part, anc);
+                           fold_vec, a, st_ws, st_user, n_w, n_part, anc, rc);
         break;
     }
     return check_launch("resample kernel (one launch)");
 }
 
 int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_stats* st_user, int32_t* anc,
-                     hipStream_t stream)
+                     hipStream_t stream, const RowCopy& rc)
 {
     if (n <= (p.variant == kMegopolis ? kSmallMaxN : kSmallMaxNOther))
-        return enqueue_small(w, n, p, ws, st_user, anc, stream);
+        return enqueue_small(w, n, p, ws, st_user, anc, stream, rc);
     if (p.variant == kMegopolis && n <= kSplitFusedMaxN) {
         // two launches: the reduction (partials and mirror), then the split
         // accept loop with the finalize step done in every block
         uint32_t g = 0;
-        int rc = enqueue_reduce(w, n, p, true, ws, &g, stream);
-        if (rc) return rc;
+        const int err = enqueue_reduce(w, n, p, true, ws, &g, stream);
+        if (err) return err;
         SplitArgs f{};
         f.parts = reinterpret_cast<const Partial*>(ws + kWsPartialsOffset);
         f.nparts = g;
@@ -772,12 +823,12 @@ int enqueue_resample(const float* w, uint32_t n, const Params& p, char* ws, mgp_
         const float* mirror = reinterpret_cast<const float*>(ws + mirror_offset(p.b_max));
         hipLaunchKernelGGL(k_megopolis_split<kSplitFinalize>, dim3((n + 63u) / 64u), dim3(kLoopThreads), 0, stream,
                            mirror, n, n, nullptr, nullptr, f.a.key0, f.a.key1, p.stream_id, f.a.tag, p.b_max,
-                           p.segment - 1u, anc, f);
+                           p.segment - 1u, anc, f, rc);
         return check_launch("megopolis kernel (finalize and split loop)");
     }
-    int rc = enqueue_reduce_finalize(w, n, p, p.variant == kMegopolis, ws, st_user, stream);
-    if (rc) return rc;
-    return enqueue_loop(w, n, p, ws, anc, stream);
+    int err = enqueue_reduce_finalize(w, n, p, p.variant == kMegopolis, ws, st_user, stream);
+    if (err) return err;
+    return enqueue_loop(w, n, p, ws, anc, stream, rc);
 }
 
 // One element (or float4) per thread up to 2^20 blocks, grid-stride beyond.
@@ -828,6 +879,30 @@ int mgp_workspace_size(int32_t n, const mgp_params* params, size_t* bytes)
     int rc = normalize_params(params, &p);
     if (rc) return rc;
     *bytes = workspace_bytes((uint32_t)n, p);
+    return MGP_OK;
+}
+
+// Whether n_out rows of d floats at out overlap n_in rows at in.
+static bool overlaps(const float* in, int32_t n_in, const float* out, int32_t n_out, int32_t d)
+{
+    const uint64_t in_bytes = (uint64_t)n_in * (uint64_t)d * 4u;
+    const uint64_t out_bytes = (uint64_t)n_out * (uint64_t)d * 4u;
+    const uintptr_t a0 = (uintptr_t)in, a1 = a0 + in_bytes;
+    const uintptr_t b0 = (uintptr_t)out, b1 = b0 + out_bytes;
+    return out_bytes && a0 < b1 && b0 < a1;
+}
+
+// The row copy of the fused entry points: n rows of d floats from states to
+// out; float4 moves when d % 4 == 0 and both buffers are 16-byte aligned.
+static int row_copy_args(const float* states, int32_t n, int32_t d, float* out, RowCopy* rc)
+{
+    if (!states || !out) return fail(MGP_EINVAL, "states_dev and out_dev must not be NULL");
+    if (d < 1) return fail(MGP_EINVAL, "d must be >= 1 (got %d)", d);
+    if (overlaps(states, n, out, n, d)) return fail(MGP_EINVAL, "out_dev overlaps states_dev");
+    rc->states = states;
+    rc->out = out;
+    rc->d = (uint32_t)d;
+    rc->vec4 = (d % 4 == 0 && ((uintptr_t)states & 15u) == 0 && ((uintptr_t)out & 15u) == 0) ? 1u : 0u;
     return MGP_OK;
 }
 
@@ -978,13 +1053,47 @@ int mgp_gather(const float* states_dev, int32_t n_states, int32_t d, const int32
     clear_error();
     if (!states_dev || !ancestors_dev || !out_dev) return fail(MGP_EINVAL, "NULL pointer argument");
     if (n_states < 1 || d < 1 || n_out < 0) return fail(MGP_EINVAL, "need n_states >= 1, d >= 1, n_out >= 0");
-    const uint64_t in_bytes = (uint64_t)n_states * (uint64_t)d * 4u;
-    const uint64_t out_bytes = (uint64_t)n_out * (uint64_t)d * 4u;
-    const uintptr_t a0 = (uintptr_t)states_dev, a1 = a0 + in_bytes;
-    const uintptr_t b0 = (uintptr_t)out_dev, b1 = b0 + out_bytes;
-    if (out_bytes && a0 < b1 && b0 < a1) return fail(MGP_EINVAL, "out_dev overlaps states_dev");
+    if (overlaps(states_dev, n_states, out_dev, n_out, d)) return fail(MGP_EINVAL, "out_dev overlaps states_dev");
     return enqueue_gather(states_dev, (uint32_t)n_states, (uint32_t)d, ancestors_dev, (uint32_t)n_out, out_dev,
                           static_cast<hipStream_t>(stream));
+}
+
+int mgp_resample_gather(const float* w_dev, int32_t n, const mgp_params* params, const float* states_dev, int32_t d,
+                        int32_t* ancestors_dev, float* out_dev, mgp_stats* stats_dev, void* workspace_dev,
+                        size_t workspace_bytes_, void* stream)
+{
+    clear_error();
+    if (!w_dev) return fail(MGP_EINVAL, "w_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    RowCopy rc;
+    int err = row_copy_args(states_dev, n, d, out_dev, &rc);
+    if (err) return err;
+    Params p;
+    err = normalize_params(params, &p);
+    if (err) return err;
+    err = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
+    if (err) return err;
+    return enqueue_resample(w_dev, (uint32_t)n, p, static_cast<char*>(workspace_dev), stats_dev, ancestors_dev,
+                            static_cast<hipStream_t>(stream), rc);
+}
+
+int mgp_resample_gather_prepared(const float* w_dev, int32_t n, const mgp_params* params, const float* states_dev,
+                                 int32_t d, int32_t* ancestors_dev, float* out_dev, void* workspace_dev,
+                                 size_t workspace_bytes_, void* stream)
+{
+    clear_error();
+    if (!w_dev) return fail(MGP_EINVAL, "w_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    RowCopy rc;
+    int err = row_copy_args(states_dev, n, d, out_dev, &rc);
+    if (err) return err;
+    Params p;
+    err = normalize_params(params, &p);
+    if (err) return err;
+    err = check_workspace(workspace_dev, workspace_bytes_, (uint32_t)n, p);
+    if (err) return err;
+    return enqueue_loop(w_dev, (uint32_t)n, p, static_cast<char*>(workspace_dev), ancestors_dev,
+                        static_cast<hipStream_t>(stream), rc);
 }
 
 }  // extern "C"

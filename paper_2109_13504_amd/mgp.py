@@ -135,6 +135,10 @@ def lib():
         L.mgp_resample_noalloc.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, _vp]
         L.mgp_resample_prepared.argtypes = [_vp, ctypes.c_int32, P, _vp, _vp, ctypes.c_size_t, _vp]
         L.mgp_gather.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+        L.mgp_resample_gather.argtypes = [_vp, ctypes.c_int32, P, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                          ctypes.c_size_t, _vp]
+        L.mgp_resample_gather_prepared.argtypes = [_vp, ctypes.c_int32, P, _vp, ctypes.c_int32, _vp, _vp, _vp,
+                                                   ctypes.c_size_t, _vp]
         L.mgp_batch_plan_create.argtypes = [ctypes.POINTER(mgp_filter_desc), ctypes.c_int32,
                                             ctypes.POINTER(mgp_batch_config), _vp, ctypes.POINTER(_vp)]
         L.mgp_batch_set_seeds.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64), _vp]
@@ -172,11 +176,14 @@ def lib():
                   "mgp_sir_resample", "mgp_sir_estimate", "mgp_sir_run", "mgp_sir_results", "mgp_sir_get_buffers",
                   "mgp_sir_destroy"):
             getattr(L, f).restype = ctypes.c_int
+        L.mgp_probe_stream_read.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+        L.mgp_probe_stream_read.restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
         L.mgp_version.argtypes = []
         for f in ("mgp_workspace_size", "mgp_resample", "mgp_resample_m", "mgp_resample_noalloc", "mgp_compute_B",
-                  "mgp_resample_prepared", "mgp_gather", "mgp_version"):
+                  "mgp_resample_prepared", "mgp_gather", "mgp_resample_gather", "mgp_resample_gather_prepared",
+                  "mgp_version"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -246,6 +253,21 @@ def mgp_resample_prepared(w_dev: int, n: int, params: mgp_params, ancestors_dev:
 def mgp_gather(states_dev: int, n_states: int, d: int, ancestors_dev: int, n_out: int, out_dev: int,
                stream: int) -> None:
     _check(lib().mgp_gather(states_dev, n_states, d, ancestors_dev, n_out, out_dev, stream or None), "mgp_gather")
+
+
+def mgp_resample_gather(w_dev: int, n: int, params: mgp_params, states_dev: int, d: int, ancestors_dev: int,
+                        out_dev: int, stats_dev: int, workspace_dev: int, workspace_bytes: int, stream: int) -> None:
+    _check(lib().mgp_resample_gather(w_dev, n, ctypes.byref(params), states_dev, d, ancestors_dev or None, out_dev,
+                                     stats_dev or None, workspace_dev, workspace_bytes, stream or None),
+           "mgp_resample_gather")
+
+
+def mgp_resample_gather_prepared(w_dev: int, n: int, params: mgp_params, states_dev: int, d: int,
+                                 ancestors_dev: int, out_dev: int, workspace_dev: int, workspace_bytes: int,
+                                 stream: int) -> None:
+    _check(lib().mgp_resample_gather_prepared(w_dev, n, ctypes.byref(params), states_dev, d, ancestors_dev or None,
+                                              out_dev, workspace_dev, workspace_bytes, stream or None),
+           "mgp_resample_gather_prepared")
 
 
 def mgp_batch_plan_create(filters, config: mgp_batch_config, stream: int) -> int:
@@ -386,6 +408,11 @@ def mgp_sir_destroy(filt: int) -> None:
     _check(lib().mgp_sir_destroy(filt), "mgp_sir_destroy")
 
 
+def mgp_probe_stream_read(buf_dev: int, nbytes: int, passes: int, blocks: int, sink_dev: int, stream: int) -> None:
+    _check(lib().mgp_probe_stream_read(buf_dev, nbytes, passes, blocks, sink_dev, stream or None),
+           "mgp_probe_stream_read")
+
+
 # ---------------------------------------------------------------------------
 # torch helpers
 # ---------------------------------------------------------------------------
@@ -483,6 +510,50 @@ class Resampler:
         mgp_resample_prepared(w.data_ptr(), n, p, out.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
                               current_stream() if stream is None else stream)
         return out
+
+    def _rows(self, w, states, out, anc, with_anc: bool):
+        """Checks the states [n, d] and allocates the outputs of a fused call."""
+        torch = _torch()
+        n = w.numel()
+        if states.dtype != torch.float32 or not states.is_cuda or not states.is_contiguous() or states.dim() < 1:
+            raise ValueError("states must be a contiguous fp32 device tensor [n, d]")
+        st2 = states.view(states.shape[0], -1)
+        if st2.shape[0] != n or st2.device != w.device:
+            raise ValueError(f"states must hold {n} rows on {w.device}")
+        d = st2.shape[1]
+        if out is None:
+            out = torch.empty((n, d), dtype=torch.float32, device=w.device)
+        _require_buffer(out, n * d, torch.float32, "out (x_bar)", w.device)
+        if anc is None and with_anc:
+            anc = torch.empty(n, dtype=torch.int32, device=w.device)
+        if anc is not None:
+            _require_buffer(anc, n, torch.int32, "anc (ancestors)", w.device)
+        return st2, d, out, anc
+
+    def resample_gather(self, w, states, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0,
+                        stream_id: int = 0, partition_bytes: int = 128, out=None, anc=None, with_anc: bool = True,
+                        stream: int | None = None, segment: int = 32):
+        """mgp_resample_gather: returns (x_bar [n, d], ancestors or None)."""
+        self._check_weights(w)
+        st2, d, out, anc = self._rows(w, states, out, anc, with_anc)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
+        mgp_resample_gather(w.data_ptr(), w.numel(), p, st2.data_ptr(), d, anc.data_ptr() if anc is not None else 0,
+                            out.data_ptr(), self.stats.data_ptr(), self.workspace.data_ptr(), self.ws_bytes,
+                            current_stream() if stream is None else stream)
+        return out, anc
+
+    def resample_gather_prepared(self, w, states, variant="megopolis", B: int = 0, epsilon: float = 0.01,
+                                 seed: int = 0, stream_id: int = 0, partition_bytes: int = 128, out=None, anc=None,
+                                 with_anc: bool = True, stream: int | None = None, segment: int = 32):
+        """The accept loop with the particle copy only, after compute_B with the same arguments."""
+        self._check_weights(w)
+        st2, d, out, anc = self._rows(w, states, out, anc, with_anc)
+        p = make_params(variant, B, epsilon, seed, stream_id, partition_bytes, self.b_max, segment)
+        mgp_resample_gather_prepared(w.data_ptr(), w.numel(), p, st2.data_ptr(), d,
+                                     anc.data_ptr() if anc is not None else 0, out.data_ptr(),
+                                     self.workspace.data_ptr(), self.ws_bytes,
+                                     current_stream() if stream is None else stream)
+        return out, anc
 
     def last_stats(self) -> dict:
         return decode_stats(self.stats)

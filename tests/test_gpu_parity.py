@@ -145,9 +145,11 @@ def test_n2pow24_sampled(torch_dev, mgp):
 
 def test_n2pow24_full_array_megopolis(torch_dev, mgp):
     """Every ancestor and every gathered row at N = 2^24, y = 4, D = 8, in the
-    benchmark's launch sequence (mgp_compute_B, mgp_resample_prepared,
-    mgp_gather). The oracle's chains are split over the host's cores (its
-    calls share no state), about 6 x 10^9 chain steps in all."""
+    benchmark's launch sequence (mgp_compute_B, then mgp_resample_gather_prepared:
+    the accept loop with the fused particle copy), and in the unfused sequence
+    (mgp_compute_B, mgp_resample_prepared, mgp_gather). The oracle's chains are
+    split over the host's cores (its calls share no state), about 6 x 10^9
+    chain steps in all."""
     import os
     from concurrent.futures import ThreadPoolExecutor
     torch, dev = torch_dev
@@ -156,18 +158,25 @@ def test_n2pow24_full_array_megopolis(torch_dev, mgp):
     wd, sd = _to_dev(torch, dev, w), _to_dev(torch, dev, st)
     r = mgp.Resampler(n)
     r.compute_B(wd, "megopolis", epsilon=0.01, seed=99)
-    anc_d = r.resample_prepared(wd, "megopolis", epsilon=0.01, seed=99)
-    out = mgp.gather(sd, anc_d).cpu().numpy()
+    out_d, anc_d = r.resample_gather_prepared(wd, sd, "megopolis", epsilon=0.01, seed=99)
+    out = out_d.cpu().numpy()
     anc = anc_d.cpu().numpy()
+    del out_d
     stats = r.last_stats()
     _check_stats(stats, w)
+    r.compute_B(wd, "megopolis", epsilon=0.01, seed=99)
+    anc_u = r.resample_prepared(wd, "megopolis", epsilon=0.01, seed=99)
+    assert torch.equal(anc_u, anc_d)
+    out_u = mgp.gather(sd, anc_u).cpu().numpy()
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
     parts = np.array_split(np.arange(n, dtype=np.int32), 4 * threads)
     with ThreadPoolExecutor(threads) as ex:
         ref = np.concatenate(list(ex.map(lambda idx: oracle.resample_subset(w, "megopolis", stats["B"], 99, idx),
                                          parts)))
     np.testing.assert_array_equal(anc, ref)
-    np.testing.assert_array_equal(out, st[anc])
+    rows = st[ref]
+    np.testing.assert_array_equal(out, rows)
+    np.testing.assert_array_equal(out_u, rows)
 
 
 def test_megopolis_uniform_weights_permutation_at_scale(torch_dev, mgp):

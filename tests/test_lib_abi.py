@@ -87,6 +87,14 @@ def test_argument_errors_before_any_device_call(mgp):
     with pytest.raises(mgp.MgpError) as e:
         mgp.mgp_gather(0, 10, 4, 0, 10, 0, 0)
     assert e.value.code == mgp.MGP_EINVAL
+    # the fused entry points check the row arguments before any device work
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_resample_gather(16, 10, mgp.make_params(B=3), 0, 4, 0, 16, 0, 0, 0, 0)
+    assert e.value.code == mgp.MGP_EINVAL
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_resample_gather_prepared(16, 10, mgp.make_params(B=3), 256, 0, 0, 4096, 0, 0, 0)
+    assert e.value.code == mgp.MGP_EINVAL
+    assert "d must be" in mgp.mgp_last_error()
 
 
 def test_noalloc_size_limit_checked_on_the_host(mgp):

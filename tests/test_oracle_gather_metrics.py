@@ -41,3 +41,29 @@ def test_mse_of_multinomial_resampling_closed_form():
     expect = np.sum(n * wb * (1 - wb)) / n
     assert abs(q.mse_over_n() - expect) < 5 * q.mse_over_n_stderr()
     assert q.bias_contribution() < 0.05
+
+
+def test_variance_sum_and_debiased_bias_on_multinomial():
+    """For multinomial resampling Var o^(i) = N w_bar_i (1 - w_bar_i) and the
+    bias is zero, so the K-sample ||Bias||^2 is all finite-K noise: its
+    debiased value is near zero while the raw one is near sum Var / K."""
+    n = 200
+    w = inputs.gaussian_weights(n, 1.5, 7).astype(np.float64)
+    wb = w / w.sum()
+    g = np.random.Generator(np.random.PCG64(11))
+    q = QualityAccumulator(w)
+    K = 4000
+    for _ in range(K):
+        q.add(np.repeat(np.arange(n), g.multinomial(n, wb)))
+    var_true = float(np.sum(n * wb * (1 - wb)))
+    assert abs(q.variance_sum() - var_true) < 0.03 * var_true
+    assert abs(q.bias_sq() - var_true / K) < 0.2 * var_true / K
+    assert abs(q.bias_sq_debiased()) < 0.2 * var_true / K
+    # a planted bias (every count shifted toward particle 0) is seen
+    qb = QualityAccumulator(w)
+    for _ in range(200):
+        o = g.multinomial(n, wb)
+        o[0] += 1
+        o[1] -= 1 if o[1] > 0 else 0
+        qb.add(np.repeat(np.arange(n), o))
+    assert qb.bias_sq_debiased() > 0.5

@@ -77,3 +77,20 @@ def test_subset_rejects_bad_input():
         oracle.resample_subset(w, "megopolis", 5, 1, [-1])
     with pytest.raises(oracle.OracleError):
         oracle.resample_subset(w, "megopolis", 5, 1, [3], segment=48)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_subset_accept_count_equals_full_resample(variant):
+    """The subset's accepted-step count over every particle equals the full
+    resample's; with uniform weights every step is accepted (u <= 1)."""
+    n = 1000
+    w = inputs.gaussian_weights(n, 3.0, 2)
+    everyone = np.arange(n, dtype=np.int32)
+    for B in (5, 23):
+        _, acc_full = oracle.resample(w, variant, B, 40 + B, stream_id=1, return_accepts=True)
+        _, acc_sub = oracle.resample_subset(w, variant, B, 40 + B, everyone, stream_id=1, return_accepts=True)
+        assert acc_sub == acc_full
+        assert 0 < acc_full < n * B
+    ones = np.full(n, 0.5, dtype=np.float32)
+    _, acc = oracle.resample_subset(ones, variant, 7, 3, everyone[:100], return_accepts=True)
+    assert acc == 100 * 7
