@@ -96,6 +96,18 @@ def lib():
         L.mgp_oracle_sir_predict_update.restype = None
         L.mgp_oracle_mean.argtypes = [_f32p, ctypes.c_int32]
         L.mgp_oracle_mean.restype = ctypes.c_double
+        L.mgp_oracle_prefix_scale.argtypes = [ctypes.c_float, ctypes.c_int32]
+        L.mgp_oracle_prefix_scale.restype = ctypes.c_int
+        L.mgp_oracle_prefix_fixed.argtypes = [ctypes.c_float, ctypes.c_int]
+        L.mgp_oracle_prefix_fixed.restype = ctypes.c_uint64
+        L.mgp_oracle_prefix_sum.argtypes = [_f32p, ctypes.c_int32, _u64p, ctypes.POINTER(ctypes.c_int)]
+        L.mgp_oracle_prefix_sum.restype = ctypes.c_int
+        L.mgp_oracle_prefix_threshold.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint64,
+                                                  ctypes.c_uint32, ctypes.c_uint32]
+        L.mgp_oracle_prefix_threshold.restype = ctypes.c_uint64
+        L.mgp_oracle_resample_prefix.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint64,
+                                                 ctypes.c_uint32, _u64p, _i32p]
+        L.mgp_oracle_resample_prefix.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -306,3 +318,52 @@ def sir_filter(x0: np.ndarray, z: np.ndarray, variant, B: int, seed: int, run: i
         bs.append(b)
         sts.append(st.status)
     return np.array(est), np.array(bs, dtype=np.int64), np.array(sts, dtype=np.int64), xbar
+
+
+# ---------------------------------------------------------------------------
+# Prefix-sum resamplers (Algorithms 7 and 8)
+# ---------------------------------------------------------------------------
+PREFIX_METHODS = {"multinomial": 0, "systematic": 1}
+
+
+def _method(m) -> int:
+    return PREFIX_METHODS[m] if isinstance(m, str) else int(m)
+
+
+def prefix_scale(w_max: float, n: int) -> int:
+    """The fixed-point exponent K of n weights with maximum w_max."""
+    return int(lib().mgp_oracle_prefix_scale(float(np.float32(w_max)), int(n)))
+
+
+def prefix_fixed(w: float, K: int) -> int:
+    """q = floor(w 2^K) of one fp32 weight."""
+    return int(lib().mgp_oracle_prefix_fixed(float(np.float32(w)), int(K)))
+
+
+def prefix_sum(w: np.ndarray):
+    """(inclusive fixed-point prefix sums as uint64, K)."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    incl = np.empty(w.size, dtype=np.uint64)
+    K = ctypes.c_int()
+    rc = lib().mgp_oracle_prefix_sum(_ptr(w, _f32p), w.size, _ptr(incl, _u64p), ctypes.byref(K))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_prefix_sum")
+    return incl, K.value
+
+
+def prefix_threshold(method, S: int, n: int, seed: int, stream_id: int, i: int) -> int:
+    return int(lib().mgp_oracle_prefix_threshold(_method(method), int(S), int(n), int(seed) & (2**64 - 1),
+                                                 int(stream_id), int(i)))
+
+
+def resample_prefix(w: np.ndarray, method, seed: int, stream_id: int = 0) -> np.ndarray:
+    """Multinomial ("multinomial", Algorithm 7) or systematic ("systematic",
+    Algorithm 8) resampling through the fixed-point prefix sum."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    incl = np.empty(w.size, dtype=np.uint64)
+    anc = np.empty(w.size, dtype=np.int32)
+    rc = lib().mgp_oracle_resample_prefix(_ptr(w, _f32p), w.size, _method(method), int(seed) & (2**64 - 1),
+                                          int(stream_id), _ptr(incl, _u64p), _ptr(anc, _i32p))
+    if rc:
+        raise OracleError(rc, "mgp_oracle_resample_prefix")
+    return anc

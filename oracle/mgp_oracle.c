@@ -21,6 +21,9 @@
  *   - particle copy x_bar_i = x_k    : last statement of Algorithms 2-5
  *   - M != N resampling              : the closing discussion (Section 8)
  *   - SIR application (predict, update, estimate): Algorithm 6, Section 7
+ *   - multinomial and systematic resampling through a prefix sum of the
+ *     weights (the unbiased comparison methods): Algorithms 7 and 8
+ *     (the appendix), Section 6.5
  *
  * The paper fixes the algorithms but not the random-number generator (it used
  * a stateful generator on its GPU). Here every random draw is a pure function
@@ -38,6 +41,8 @@
  *   tag 3  C1 partition   index = group g,    block = 0,     word 0
  *   tag 4  C2 partition   index = group g,    block = b / 4, word b % 4
  *   tag 5  SIR noise      index = i / 4,      block = step t, Box-Muller pairs
+ *   tag 6  multinomial    index = output i,   block = 0,     words 0-1: one 64-bit draw
+ *   tag 7  systematic     index = 0,          block = 0,     words 0-1: one 64-bit draw
  *
  * with group g = floor(i / 32) (the paper's warp index). Maps from 32-bit words:
  *   u in (0,1]   : m = 24 random bits, u = (m + 1) * 2^-24   (exact in fp32)
@@ -453,4 +458,115 @@ double mgp_oracle_mean(const float* x, int32_t n)
     double s = 0.0;
     for (int32_t i = 0; i < n; ++i) s += (double)x[i];
     return s / (double)n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Prefix-sum resamplers (the unbiased comparison methods of Section 6.5 and */
+/* Table 2): multinomial resampling (Algorithm 7) and systematic resampling  */
+/* (Algorithm 8). Both find, for each output i, the first input j whose      */
+/* inclusive prefix sum of weights exceeds a threshold t_i: multinomial with */
+/* an independent uniform t_i per output, systematic with the evenly spaced  */
+/* t_i = (i + u) S / N from one uniform u. The prefix sum runs on the        */
+/* weights in 64-bit fixed point, where it is exact.                         */
+/* ------------------------------------------------------------------------ */
+#define OR_MULTINOMIAL 0
+#define OR_SYSTEMATIC 1
+#define OR_TAG_MULTINOMIAL 6u
+#define OR_TAG_SYSTEMATIC 7u
+
+/* The fixed-point exponent K of n weights whose maximum is w_max > 0: with
+ * w_max = m 2^E, m in [0.5, 1), K = 62 - ceil(log2 n) - E. Then every
+ * q_i = floor(w_i 2^K) is below 2^(62 - ceil(log2 n)) and n of them sum to
+ * less than 2^62. */
+int mgp_oracle_prefix_scale(float w_max, int32_t n)
+{
+    int E = 0;
+    frexp((double)w_max, &E);
+    int L = 0;
+    while (((int64_t)1 << L) < (int64_t)n) ++L;
+    return 62 - L - E;
+}
+
+/* q = floor(w 2^K): exact in fp64 (a power-of-two scaling of an fp32 value
+ * stays inside fp64's range for every K the scale above can give). */
+uint64_t mgp_oracle_prefix_fixed(float w, int K)
+{
+    return (uint64_t)floor(ldexp((double)w, K));
+}
+
+/* Inclusive prefix sums incl[j] = q_0 + ... + q_j, in index order. Returns
+ * OR_EWEIGHTS for invalid weights (as mgp_oracle_reduce); *K_out gets K. */
+int mgp_oracle_prefix_sum(const float* w, int32_t n, uint64_t* incl, int* K_out)
+{
+    float w_max;
+    double w_sum;
+    int rc = mgp_oracle_reduce(w, n, &w_max, &w_sum);
+    if (rc) return rc;
+    int K = mgp_oracle_prefix_scale(w_max, n);
+    uint64_t run = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        run += mgp_oracle_prefix_fixed(w[j], K);
+        incl[j] = run;
+    }
+    if (K_out) *K_out = K;
+    return OR_OK;
+}
+
+/* The threshold t_i in [0, S) of output i, S the total of the fixed-point
+ * weights.
+ *   multinomial (Algorithm 7: u ~ U[0, total)): a 64-bit draw r from words 0
+ *     and 1 of Philox call (0, tag 6, stream_id, i), t = floor(r S / 2^64);
+ *   systematic (Algorithm 8: u = (i + u_t) / N after one draw u_t ~ U[0, 1)):
+ *     u_t = (r >> 11) 2^-53 from the 64-bit draw r of call (0, tag 7,
+ *     stream_id, 0), then in fp64 with the rounding of each operation
+ *     c = S / N, v = (i + u_t) c, t = floor(v), and t = S - 1 should the
+ *     rounding take v to S. */
+uint64_t mgp_oracle_prefix_threshold(int method, uint64_t S, int32_t n, uint64_t seed, uint32_t stream_id,
+                                     uint32_t i)
+{
+    uint32_t x[4];
+    if (method == OR_MULTINOMIAL) {
+        draw_words(seed, OR_TAG_MULTINOMIAL, stream_id, i, 0u, x);
+        uint64_t r = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+        return (uint64_t)(((unsigned __int128)r * (unsigned __int128)S) >> 64);
+    }
+    draw_words(seed, OR_TAG_SYSTEMATIC, stream_id, 0u, 0u, x);
+    uint64_t r = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    double ut = (double)(r >> 11) * 0x1p-53;
+    double c = (double)S / (double)n;
+    double v = ((double)i + ut) * c;
+    uint64_t t = (uint64_t)floor(v);
+    return t < S ? t : S - 1u;
+}
+
+/* The first j with incl[j] > t (incl nondecreasing, incl[n-1] > t), by
+ * bisection. */
+static int32_t first_above(const uint64_t* incl, int32_t n, uint64_t t)
+{
+    int32_t lo = 0, hi = n - 1; /* the answer lies in [lo, hi] */
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (incl[mid] > t)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+/* Multinomial (method 0) or systematic (method 1) resampling of n weighted
+ * particles: ancestors[i] = the first j with incl[j] > t_i. incl_scratch
+ * holds n entries. Zero weights repeat the prefix sum and are never chosen. */
+int mgp_oracle_resample_prefix(const float* w, int32_t n, int method, uint64_t seed, uint32_t stream_id,
+                               uint64_t* incl_scratch, int32_t* ancestors)
+{
+    if (n < 1 || (method != OR_MULTINOMIAL && method != OR_SYSTEMATIC) || !incl_scratch) return OR_EINVAL;
+    int rc = mgp_oracle_prefix_sum(w, n, incl_scratch, NULL);
+    if (rc) return rc;
+    uint64_t S = incl_scratch[n - 1];
+    for (int32_t i = 0; i < n; ++i) {
+        uint64_t t = mgp_oracle_prefix_threshold(method, S, n, seed, stream_id, (uint32_t)i);
+        ancestors[i] = first_above(incl_scratch, n, t);
+    }
+    return OR_OK;
 }
