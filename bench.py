@@ -64,6 +64,8 @@ def parse():
                     help="fixed batched launch shape 'block_threads,particles_per_thread,schedule' (default: autotuned)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant sweep at N=2^22")
+    ap.add_argument("--no-prefix", action="store_true",
+                    help="skip the prefix-sum methods (multinomial, systematic) against Megopolis")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--no-sir", action="store_true", help="skip the SIR filter section")
     ap.add_argument("--no-segment64", action="store_true", help="skip the 64-wide-segment Megopolis step")
@@ -504,6 +506,53 @@ def n_sweep_section(torch, mgp, inputs):
                         "(no gather); median of 5; k40m_ms from Table 3", "rows": rows}
 
 
+def prefix_section(torch, mgp, inputs):
+    """Section 6.5's comparison with the unbiased prefix-sum methods on this
+    GPU: multinomial (Algorithm 7) and systematic (Algorithm 8) resampling
+    through mgp_resample_prefix against Megopolis (mgp_resample), N = 2^16 ..
+    2^24, y = 0, 2, 4, eps = 0.01; each a whole call (reduction and validation,
+    the fixed-point prefix sum, the search), median of 5 after one warm-up."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def med(fn):
+        times = []
+        for k in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn(k)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if k:
+                times.append(a.elapsed_time(b))
+        return float(np.median(times))
+
+    for ln in (16, 20, 24):
+        n = 1 << ln
+        rp = mgp.PrefixResampler(n)
+        rm = mgp.Resampler(n)
+        anc = torch.empty(n, dtype=torch.int32, device=dev)
+        for y in (0, 2, 4):
+            w = torch.from_numpy(inputs.gaussian_weights(n, float(y), 0)).to(dev)
+            row = {}
+            for method in ("multinomial", "systematic"):
+                row[method + "_ms"] = med(lambda k: rp.resample(w, method, seed=k, out=anc))
+            row["megopolis_ms"] = med(lambda k: rm.resample(w, "megopolis", epsilon=0.01, seed=k, out=anc))
+            row["megopolis_B"] = rm.last_stats()["B"]
+            row["speedup_vs_multinomial"] = row["multinomial_ms"] / row["megopolis_ms"]
+            row["speedup_vs_systematic"] = row["systematic_ms"] / row["megopolis_ms"]
+            out[f"2^{ln}_y{y}"] = row
+            del w
+        del rp, rm, anc
+    log("[bench] prefix-sum methods: " + "; ".join(
+        f"{k} mult {v['multinomial_ms']:.3f} syst {v['systematic_ms']:.3f} mego {v['megopolis_ms']:.3f} ms"
+        for k, v in out.items()))
+    return {"workload": "Gaussian-likelihood weights, eps=0.01 for Megopolis; whole resample calls, ancestors only, "
+                        "median of 5", "rows": out}
+
+
 def m_neq_n_section(torch, mgp, inputs):
     """M != N resampling (Section 8's D-PMC remark): Megopolis, B from
     eps = 0.01 on Gaussian-likelihood weights with y = 4, N inputs -> M
@@ -779,7 +828,12 @@ def main():
         log("[bench] " + ", ".join(f"{k}: {v['ms']:.3f} ms" for k, v in result["n_sweep"]["rows"].items()))
         log("[bench] M != N")
         result["m_neq_n"] = m_neq_n_section(torch, mgp, inputs)
+
         log(f"[bench] M != N: {result['m_neq_n']['runs']}")
+
+    if not args.no_prefix:
+        log("[bench] prefix-sum methods")
+        result["prefix_sum_methods"] = prefix_section(torch, mgp, inputs)
 
     if not args.no_serving:
         log("[bench] serving")

@@ -481,6 +481,40 @@ const char* mgp_last_error(void);
 /* Library version, major * 10000 + minor * 100 + patch. */
 int mgp_version(void);
 
+/* ---- prefix-sum resamplers (the unbiased comparison methods) ------------
+ * Multinomial (Algorithm 7) and systematic (Algorithm 8) resampling, the
+ * methods Section 6.5 and Table 2 compare Megopolis with. Each output i gets
+ * the first input j whose inclusive prefix sum of weights exceeds a threshold
+ * t_i in [0, S):
+ *   MGP_MULTINOMIAL: t_i = floor(r_i S / 2^64), r_i an independent 64-bit
+ *                    draw per output (Philox counter (0, 6, stream_id, i));
+ *   MGP_SYSTEMATIC:  t_i = floor((i + u) S / N) in fp64, one draw u in [0, 1)
+ *                    per call (Philox counter (0, 7, stream_id, 0)).
+ * The prefix sum runs on 64-bit fixed-point weights q_j = floor(w_j 2^K),
+ * K = 62 - ceil(log2 N) - E where max w = m 2^E, m in [0.5, 1): exact in any
+ * summation order, S < 2^62. Weights below 2^-(62 - ceil(log2 N)) of the
+ * largest become 0 and are never chosen. */
+typedef enum mgp_prefix_method {
+    MGP_MULTINOMIAL = 0, /* Algorithm 7 */
+    MGP_SYSTEMATIC = 1   /* Algorithm 8 */
+} mgp_prefix_method;
+
+/* Bytes of device workspace mgp_resample_prefix needs for n particles
+ * (about 8n: the prefix sums). Host-only. */
+int mgp_prefix_workspace_size(int32_t n, size_t* bytes);
+
+/* Ancestors by multinomial or systematic resampling, all on `stream`: the
+ * reduction and validation of mgp_resample (stats_dev as there, with B = 1),
+ * the fixed-point prefix sum, then one threshold and bisection per output.
+ * w_dev: n fp32 weights (device), >= 0, finite, not all zero (else stats
+ * status MGP_EWEIGHTS and every ancestor -1). ancestors_dev: n int32
+ * (device), written. method: mgp_prefix_method. seed, stream_id: the Philox
+ * key and counter word 2. workspace_dev: mgp_prefix_workspace_size bytes,
+ * 256-byte aligned, caller-owned scratch. */
+int mgp_resample_prefix(const float* w_dev, int32_t n, int32_t method, uint64_t seed, uint32_t stream_id,
+                        int32_t* ancestors_dev, mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes,
+                        void* stream);
+
 /* ---- memory-system probe -------------------------------------------------
  * The streaming-read rate of the device at one buffer size: the benchmark
  * reports it as the memory ceiling beside the accept loop's achieved rate

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmgp.so")
 
-SOURCES = ["mgp_kernels.hip", "mgp_batch.hip", "mgp_serve.hip", "mgp_sir.hip", "mgp_probe.hip"]
+SOURCES = ["mgp_kernels.hip", "mgp_batch.hip", "mgp_serve.hip", "mgp_sir.hip", "mgp_probe.hip", "mgp_prefix.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

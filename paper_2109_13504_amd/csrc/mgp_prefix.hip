@@ -1,0 +1,464 @@
+// mgp_prefix.hip -- the prefix-sum resamplers of the C ABI (include/mgp.h):
+// multinomial (Algorithm 7) and systematic (Algorithm 8) resampling, the
+// unbiased comparison methods of Section 6.5 and Table 2.
+//
+// Both give output i the first input j whose inclusive prefix sum of weights
+// exceeds a threshold t_i (multinomial: an independent uniform t_i per
+// output; systematic: t_i = (i + u) S / N from one uniform u). The weights
+// enter the prefix sum as 64-bit fixed point, q = floor(w 2^K), with K from
+// the largest weight such that the total S stays below 2^62: integer sums are
+// exact in any order, so the parallel scan here and a sequential sum give the
+// same prefix and the same ancestors.
+//
+// The search runs down a 16-ary tree over the prefix sums: level 0 is the
+// inclusive sums themselves, level k holds every 16^k-th of them (the sum at
+// the end of each group of 16^k inputs), and the top level has at most 16
+// entries. A lane reads one 128-byte row of 16 sums per level and counts the
+// sums <= t, which is the child to descend into.
+//
+// Launches: the reduction and finalize step of the other resamplers
+// (validation, max, fp64 sum), then
+//   k_prefix_chunks   per chunk of kChunk weights: the fixed-point chunk sum
+//   k_prefix_top      one block: exclusive sums over the chunks, the header
+//   k_prefix_scan     per chunk: the inclusive sums (coalesced through LDS)
+//                     and the tree's entries that fall in the chunk
+//   multinomial:      k_prefix_multinomial, a descent per output
+//   systematic:       k_prefix_brackets, a descent for every 256th output,
+//                     then k_prefix_systematic, a bisection per output between
+//                     the two brackets of its group (thresholds rise with i)
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "mgp.h"
+#include "mgp_device.h"
+#include "mgp_internal.h"
+
+namespace mgp {
+
+constexpr uint32_t kPrefixThreads = 256;
+constexpr uint32_t kPrefixPer = 8;                        // weights per thread in a chunk
+constexpr uint32_t kChunk = kPrefixThreads * kPrefixPer;  // 2048 weights per chunk
+constexpr uint32_t kFan = 16;                             // the tree's fan-out: one 128-byte row of sums
+constexpr int kMaxLevels = 8;                             // 16^8 = 2^32 > any n
+constexpr uint32_t kTagMultinomial = 6u;
+constexpr uint32_t kTagSystematic = 7u;
+
+// What the scan leaves for the search (in the workspace).
+struct PrefixHeader {
+    uint64_t total;  // S, the sum of the fixed-point weights (0: invalid weights)
+    int32_t K;       // the fixed-point exponent
+    int32_t valid;   // 1 when the weights passed validation
+};
+
+// The tree above level 0: level k (1..top) at t[k], with count[k] real
+// entries (the last is S), padded with S to a multiple of kFan.
+struct Tree {
+    uint64_t* t[kMaxLevels + 1];
+    uint32_t count[kMaxLevels + 1];
+    int top;  // 0 when n <= kFan (level 0 alone)
+};
+
+// K = 62 - ceil(log2 n) - E for w_max = m 2^E, m in [0.5, 1).
+__device__ __forceinline__ int fixed_exponent(float w_max, int log2n_ceil)
+{
+    int E = 0;
+    frexp((double)w_max, &E);
+    return 62 - log2n_ceil - E;
+}
+
+// q = floor(w 2^K) for a finite w >= 0, from its fields: w = m 2^(e - 150)
+// with m = 2^23 + mantissa for a normal w (biased exponent e >= 1), and
+// w = mantissa 2^-149 for a subnormal one; the shift by e - 150 + K is exact
+// (a right shift floors).
+__device__ __forceinline__ uint64_t fixed_weight(float w, int K)
+{
+    const uint32_t bits = __float_as_uint(w) & 0x7FFFFFFFu;  // -0.0 is 0
+    const uint32_t e = bits >> 23;
+    const uint64_t m = e ? (uint64_t)((bits & 0x7FFFFFu) | 0x800000u) : (uint64_t)bits;
+    const int sh = (e ? (int)e - 150 : -149) + K;
+    if (sh >= 0) return m << sh;
+    return sh <= -64 ? 0u : m >> (-sh);
+}
+
+// Block-wide exclusive scan of one uint64 per thread; returns the thread's
+// exclusive prefix and the block total through *total.
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* total)
+{
+    __shared__ uint64_t wave_sums[kPrefixThreads / 64];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, 64);
+        if ((int)lane >= off) x += y;
+    }
+    if (lane == 63u) wave_sums[wv] = x;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPrefixThreads / 64; ++k) {
+        const uint64_t s = wave_sums[k];
+        if (k < wv) before += s;
+        all += s;
+    }
+    __syncthreads();  // wave_sums is reused by the next call
+    *total = all;
+    return before + x - v;
+}
+
+// The fixed-point weights of this thread's kPrefixPer consecutive inputs of
+// chunk `chunk` (0 past n). vec: w 16-byte aligned (n may be ragged).
+__device__ __forceinline__ void load_fixed(const float* __restrict__ w, uint32_t n, uint32_t chunk, int K, bool vec,
+                                           uint64_t (&q)[kPrefixPer])
+{
+    const uint64_t base = (uint64_t)chunk * kChunk + (uint64_t)threadIdx.x * kPrefixPer;
+    if (vec && base + kPrefixPer <= n) {
+        const float4 a = *reinterpret_cast<const float4*>(w + base);
+        const float4 b = *reinterpret_cast<const float4*>(w + base + 4);
+        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (uint32_t e = 0; e < kPrefixPer; ++e) q[e] = fixed_weight(v[e], K);
+    } else {
+#pragma unroll
+        for (uint32_t e = 0; e < kPrefixPer; ++e) q[e] = base + e < n ? fixed_weight(w[base + e], K) : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_chunks(const float* __restrict__ w, uint32_t n,
+                                                                  int log2n_ceil, uint32_t vec,
+                                                                  const mgp_stats* __restrict__ st,
+                                                                  uint64_t* __restrict__ chunk_sum)
+{
+    if (st->status != MGP_OK) {
+        if (threadIdx.x == 0) chunk_sum[blockIdx.x] = 0;
+        return;
+    }
+    uint64_t q[kPrefixPer];
+    load_fixed(w, n, blockIdx.x, fixed_exponent(st->w_max, log2n_ceil), vec != 0u, q);
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kPrefixPer; ++e) s += q[e];
+    uint64_t total = 0;
+    block_exclusive_scan(s, &total);
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
+}
+
+// One block: chunk_excl[c] = sum of chunk_sum[0..c), and the header.
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_top(const uint64_t* __restrict__ chunk_sum, uint32_t nch,
+                                                               int log2n_ceil, const mgp_stats* __restrict__ st,
+                                                               uint64_t* __restrict__ chunk_excl,
+                                                               PrefixHeader* __restrict__ hdr)
+{
+    // thread t owns chunks [t * per, (t + 1) * per)
+    const uint32_t per = (nch + kPrefixThreads - 1u) / kPrefixThreads;
+    const uint32_t c0 = threadIdx.x * per;
+    uint64_t s = 0;
+    for (uint32_t c = c0; c < c0 + per && c < nch; ++c) s += chunk_sum[c];
+    uint64_t total = 0;
+    uint64_t run = block_exclusive_scan(s, &total);
+    for (uint32_t c = c0; c < c0 + per && c < nch; ++c) {
+        chunk_excl[c] = run;
+        run += chunk_sum[c];
+    }
+    if (threadIdx.x == 0) {
+        const bool ok = st->status == MGP_OK;
+        PrefixHeader h;
+        h.total = ok ? total : 0u;
+        h.K = ok ? fixed_exponent(st->w_max, log2n_ceil) : 0;
+        h.valid = ok ? 1 : 0;
+        *hdr = h;
+    }
+}
+
+// The inclusive sums of one chunk: computed per thread over its kPrefixPer
+// inputs, passed through LDS so that each store instruction writes 512
+// contiguous bytes. Positions past n hold S (level 0 is padded to whole
+// chunks). The tree's entries that fall in the chunk are written here too:
+// level k entry m is the sum at position (m + 1) 16^k - 1, and the thread
+// holding position n - 1 writes the last real entry (S) and the padding of
+// every level.
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_scan(const float* __restrict__ w, uint32_t n, uint32_t vec,
+                                                                const PrefixHeader* __restrict__ hdr,
+                                                                const uint64_t* __restrict__ chunk_excl,
+                                                                uint64_t* __restrict__ incl, Tree tree)
+{
+    __shared__ uint64_t stage[kChunk];
+    if (!hdr->valid) return;
+    uint64_t q[kPrefixPer];
+    load_fixed(w, n, blockIdx.x, hdr->K, vec != 0u, q);
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kPrefixPer; ++e) s += q[e];
+    uint64_t total = 0;
+    uint64_t run = chunk_excl[blockIdx.x] + block_exclusive_scan(s, &total);
+    const uint64_t base = (uint64_t)blockIdx.x * kChunk;
+    const uint64_t mine = base + (uint64_t)threadIdx.x * kPrefixPer;
+#pragma unroll
+    for (uint32_t e = 0; e < kPrefixPer; ++e) {
+        run += q[e];
+        stage[threadIdx.x * kPrefixPer + e] = run;
+        const uint64_t p = mine + e;
+        if (p < n && (p + 1u) % kFan == 0u) {
+            // level k entry (p + 1) / 16^k - 1 for every k with 16^k | p + 1
+            uint64_t g = (p + 1u) / kFan;
+            for (int k = 1; k <= tree.top; ++k) {
+                tree.t[k][g - 1u] = run;
+                if (g % kFan != 0u) break;
+                g /= kFan;
+            }
+        }
+        if (p == (uint64_t)n - 1u) {
+            for (int k = 1; k <= tree.top; ++k) {
+                const uint32_t end = (tree.count[k] + kFan - 1u) / kFan * kFan;
+                for (uint32_t m = tree.count[k] - 1u; m < end; ++m) tree.t[k][m] = run;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t e = 0; e < kPrefixPer; ++e) incl[base + e * kPrefixThreads + threadIdx.x] =
+        stage[e * kPrefixThreads + threadIdx.x];
+}
+
+// The first j with incl[j] > t (t < S): down the tree, one row of kFan sums
+// per level.
+__device__ __forceinline__ uint32_t descend(uint64_t t, const Tree& tree, const uint64_t* __restrict__ incl)
+{
+    uint64_t g = 0;
+    for (int k = tree.top; k >= 0; --k) {
+        const uint64_t* row = (k ? tree.t[k] : incl) + g * kFan;
+        uint64_t v[kFan];
+#pragma unroll
+        for (uint32_t m = 0; m < kFan; m += 2) {
+            const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(row + m);
+            v[m] = x.x;
+            v[m + 1] = x.y;
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t m = 0; m < kFan; ++m) c += v[m] <= t ? 1u : 0u;
+        g = g * kFan + c;
+    }
+    return (uint32_t)g;
+}
+
+// The first j in [lo, lo + len) with a[j] > t, given a[lo + len - 1] > t.
+__device__ __forceinline__ uint32_t first_above(const uint64_t* __restrict__ a, uint32_t lo, uint32_t len, uint64_t t)
+{
+    while (len > 1u) {
+        const uint32_t half = len / 2u;
+        lo = a[lo + half - 1u] <= t ? lo + half : lo;  // [lo, lo + half) all <= t: skip them
+        len -= half;
+    }
+    return lo;
+}
+
+// The threshold of output i in [0, S).
+template <int Method>
+__device__ __forceinline__ uint64_t prefix_threshold(uint64_t S, uint32_t n, uint32_t i, uint32_t key0, uint32_t key1,
+                                                     uint32_t stream_id)
+{
+    if constexpr (Method == MGP_MULTINOMIAL) {
+        // Algorithm 7: u ~ U[0, S), one 64-bit draw per output
+        const Words x = philox(0u, kTagMultinomial, stream_id, i, key0, key1);
+        const uint64_t r = (uint64_t)x.x0 | ((uint64_t)x.x1 << 32);
+        return __umul64hi(r, S);
+    } else {
+        // Algorithm 8: u = (i + u_t) / N after one draw u_t ~ U[0, 1), in fp64
+        // with each operation rounded once
+        const Words x = philox(0u, kTagSystematic, stream_id, 0u, key0, key1);
+        const uint64_t r = (uint64_t)x.x0 | ((uint64_t)x.x1 << 32);
+        const double ut = (double)(r >> 11) * 0x1p-53;
+        const double c = __ddiv_rn((double)S, (double)n);
+        const double v = __dmul_rn(__dadd_rn((double)i, ut), c);
+        const uint64_t t = (uint64_t)floor(v);
+        return t < S ? t : S - 1u;
+    }
+}
+
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_multinomial(uint32_t n, const PrefixHeader* __restrict__ hdr,
+                                                                       Tree tree, const uint64_t* __restrict__ incl,
+                                                                       uint32_t key0, uint32_t key1,
+                                                                       uint32_t stream_id, int32_t* __restrict__ anc)
+{
+    const uint32_t i = blockIdx.x * kPrefixThreads + threadIdx.x;
+    if (i >= n) return;
+    if (!hdr->valid) {
+        anc[i] = -1;
+        return;
+    }
+    const uint64_t t = prefix_threshold<MGP_MULTINOMIAL>(hdr->total, n, i, key0, key1, stream_id);
+    anc[i] = (int32_t)descend(t, tree, incl);
+}
+
+// Systematic, first pass: the ancestors of outputs 0, G, 2G, ... (G =
+// kPrefixThreads) and n - 1, which bracket those of every output between.
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_brackets(uint32_t n, uint32_t nb,
+                                                                    const PrefixHeader* __restrict__ hdr, Tree tree,
+                                                                    const uint64_t* __restrict__ incl, uint32_t key0,
+                                                                    uint32_t key1, uint32_t stream_id,
+                                                                    uint32_t* __restrict__ bracket)
+{
+    const uint32_t b = blockIdx.x * kPrefixThreads + threadIdx.x;
+    if (b > nb || !hdr->valid) return;
+    const uint32_t i = b < nb ? b * kPrefixThreads : n - 1u;
+    bracket[b] = descend(prefix_threshold<MGP_SYSTEMATIC>(hdr->total, n, i, key0, key1, stream_id), tree, incl);
+}
+
+// Systematic, second pass: output i's ancestor lies between the brackets of
+// its group of G outputs (the thresholds, and so the ancestors, rise with
+// i). When the bracketed sums fit kStageMax entries the block reads them into
+// LDS once (coalesced) and bisects there; otherwise each lane bisects in
+// memory.
+constexpr uint32_t kStageMax = 2048;
+
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_systematic(uint32_t n, const PrefixHeader* __restrict__ hdr,
+                                                                      const uint32_t* __restrict__ bracket,
+                                                                      const uint64_t* __restrict__ incl,
+                                                                      uint32_t key0, uint32_t key1,
+                                                                      uint32_t stream_id, int32_t* __restrict__ anc)
+{
+    __shared__ uint64_t stage[kStageMax];
+    const uint32_t i = blockIdx.x * kPrefixThreads + threadIdx.x;
+    if (!hdr->valid) {
+        if (i < n) anc[i] = -1;
+        return;
+    }
+    const uint32_t lo = bracket[blockIdx.x], hi = bracket[blockIdx.x + 1u];
+    const uint32_t len = hi - lo + 1u;
+    const uint64_t t = prefix_threshold<MGP_SYSTEMATIC>(hdr->total, n, i < n ? i : n - 1u, key0, key1, stream_id);
+    if (len <= kStageMax) {  // the same for every lane of the block
+        for (uint32_t k = threadIdx.x; k < len; k += kPrefixThreads) stage[k] = incl[lo + k];
+        __syncthreads();
+        if (i < n) anc[i] = (int32_t)(lo + first_above(stage, 0u, len, t));
+    } else if (i < n) {
+        anc[i] = (int32_t)first_above(incl, lo, len, t);
+    }
+}
+
+// Workspace layout after the reduction's region (stats, partials, one
+// offset): [header][chunk sums][chunk exclusive][brackets][tree levels
+// 1..top][level 0: the inclusive sums, whole chunks].
+static size_t align256(size_t b) { return (b + 255u) & ~(size_t)255u; }
+
+struct PrefixLayout {
+    size_t hdr, chunk_sum, chunk_excl, bracket, level[kMaxLevels + 1], incl, total;
+    uint32_t count[kMaxLevels + 1];
+    int top;
+};
+
+static PrefixLayout prefix_layout(uint32_t n)
+{
+    const size_t nch = ((size_t)n + kChunk - 1u) / kChunk;
+    PrefixLayout L{};
+    L.hdr = workspace_bytes(1u);
+    L.chunk_sum = L.hdr + 256u;
+    L.chunk_excl = L.chunk_sum + align256(nch * 8u);
+    L.bracket = L.chunk_excl + align256(nch * 8u);
+    size_t at = L.bracket + align256(((size_t)n / kPrefixThreads + 2u) * 4u);
+    // level k has ceil(n / 16^k) real entries; the top is the first with <= 16
+    uint64_t cnt = n;
+    L.top = 0;
+    while (cnt > kFan) {
+        cnt = (cnt + kFan - 1u) / kFan;
+        ++L.top;
+        L.count[L.top] = (uint32_t)cnt;
+        L.level[L.top] = at;
+        at += align256((size_t)(cnt + kFan - 1u) / kFan * kFan * 8u);
+    }
+    L.incl = at;
+    L.total = L.incl + align256(nch * kChunk * 8u);
+    return L;
+}
+
+static int ceil_log2(uint32_t n)
+{
+    int L = 0;
+    while (((uint64_t)1 << L) < (uint64_t)n) ++L;
+    return L;
+}
+
+}  // namespace mgp
+
+using namespace mgp;
+
+extern "C" {
+
+int mgp_prefix_workspace_size(int32_t n, size_t* bytes)
+{
+    clear_error();
+    if (!bytes) return fail(MGP_EINVAL, "bytes is NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    *bytes = prefix_layout((uint32_t)n).total;
+    return MGP_OK;
+}
+
+int mgp_resample_prefix(const float* w_dev, int32_t n, int32_t method, uint64_t seed, uint32_t stream_id,
+                        int32_t* ancestors_dev, mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes_,
+                        void* stream)
+{
+    clear_error();
+    if (!w_dev || !ancestors_dev) return fail(MGP_EINVAL, "w_dev and ancestors_dev must not be NULL");
+    if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
+    if (method != MGP_MULTINOMIAL && method != MGP_SYSTEMATIC)
+        return fail(MGP_EINVAL, "unknown prefix-sum method %d", method);
+    if (!workspace_dev) return fail(MGP_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace_dev & 255u) != 0) return fail(MGP_EINVAL, "workspace must be 256-byte aligned");
+    const uint32_t un = (uint32_t)n;
+    const PrefixLayout L = prefix_layout(un);
+    if (workspace_bytes_ < L.total)
+        return fail(MGP_ERANGE, "workspace has %zu bytes, needs %zu", workspace_bytes_, L.total);
+    char* ws = static_cast<char*>(workspace_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // 1. validation, max and fp64 sum: the reduction and finalize step of the
+    //    other resamplers (one explicit iteration, no offsets, no mirror)
+    Params p;
+    p.variant = kMetropolis;
+    p.B = 1;
+    p.eps = 0.5;
+    p.seed = seed;
+    p.stream_id = stream_id;
+    p.partition_bytes = 128;
+    p.b_max = 1;
+    int err = enqueue_reduce_finalize(w_dev, un, p, false, ws, stats_dev, s);
+    if (err) return err;
+    const mgp_stats* st = reinterpret_cast<const mgp_stats*>(ws + kWsStatsOffset);
+    const uint32_t nch = (un + kChunk - 1u) / kChunk;
+    const int l2 = ceil_log2(un);
+    const uint32_t vec = ((uintptr_t)w_dev & 15u) == 0 ? 1u : 0u;
+    uint64_t* chunk_sum = reinterpret_cast<uint64_t*>(ws + L.chunk_sum);
+    uint64_t* chunk_excl = reinterpret_cast<uint64_t*>(ws + L.chunk_excl);
+    uint64_t* incl = reinterpret_cast<uint64_t*>(ws + L.incl);
+    PrefixHeader* hdr = reinterpret_cast<PrefixHeader*>(ws + L.hdr);
+    Tree tree{};
+    tree.top = L.top;
+    for (int k = 1; k <= L.top; ++k) {
+        tree.t[k] = reinterpret_cast<uint64_t*>(ws + L.level[k]);
+        tree.count[k] = L.count[k];
+    }
+    // 2. the fixed-point prefix sum and the tree
+    hipLaunchKernelGGL(k_prefix_chunks, dim3(nch), dim3(kPrefixThreads), 0, s, w_dev, un, l2, vec, st, chunk_sum);
+    hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kPrefixThreads), 0, s, chunk_sum, nch, l2, st, chunk_excl, hdr);
+    hipLaunchKernelGGL(k_prefix_scan, dim3(nch), dim3(kPrefixThreads), 0, s, w_dev, un, vec, hdr, chunk_excl, incl,
+                       tree);
+    err = check_launch("prefix-sum kernels");
+    if (err) return err;
+    // 3. thresholds and the search
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t nb = (un + kPrefixThreads - 1u) / kPrefixThreads;  // groups of outputs
+    if (method == MGP_MULTINOMIAL) {
+        hipLaunchKernelGGL(k_prefix_multinomial, dim3(nb), dim3(kPrefixThreads), 0, s, un, hdr, tree, incl, k0, k1,
+                           stream_id, ancestors_dev);
+    } else {
+        uint32_t* bracket = reinterpret_cast<uint32_t*>(ws + L.bracket);
+        hipLaunchKernelGGL(k_prefix_brackets, dim3(nb / kPrefixThreads + 1u), dim3(kPrefixThreads), 0, s, un, nb, hdr,
+                           tree, incl, k0, k1, stream_id, bracket);
+        hipLaunchKernelGGL(k_prefix_systematic, dim3(nb), dim3(kPrefixThreads), 0, s, un, hdr, bracket, incl, k0, k1,
+                           stream_id, ancestors_dev);
+    }
+    return check_launch("prefix-sum search kernel");
+}
+
+}  // extern "C"

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(PKG, "libmgp.so")
 
 MGP_OK, MGP_EINVAL, MGP_ERANGE, MGP_ENOMEM, MGP_EHIP, MGP_EBUSY, MGP_EWEIGHTS = 0, -1, -2, -3, -4, -5, -6
 MGP_METROPOLIS, MGP_C1, MGP_C2, MGP_MEGOPOLIS = 0, 1, 2, 3
+MGP_MULTINOMIAL, MGP_SYSTEMATIC = 0, 1
+PREFIX_METHODS = {"multinomial": MGP_MULTINOMIAL, "systematic": MGP_SYSTEMATIC}
 MGP_NOALLOC_SCRATCH_BYTES = 64 << 20
 VARIANTS = {"metropolis": MGP_METROPOLIS, "c1": MGP_C1, "c2": MGP_C2, "megopolis": MGP_MEGOPOLIS}
 
@@ -176,6 +178,11 @@ def lib():
                   "mgp_sir_resample", "mgp_sir_estimate", "mgp_sir_run", "mgp_sir_results", "mgp_sir_get_buffers",
                   "mgp_sir_destroy"):
             getattr(L, f).restype = ctypes.c_int
+        L.mgp_prefix_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.mgp_prefix_workspace_size.restype = ctypes.c_int
+        L.mgp_resample_prefix.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, _vp,
+                                          _vp, _vp, ctypes.c_size_t, _vp]
+        L.mgp_resample_prefix.restype = ctypes.c_int
         L.mgp_probe_stream_read.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
         L.mgp_probe_stream_read.restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
@@ -408,6 +415,19 @@ def mgp_sir_destroy(filt: int) -> None:
     _check(lib().mgp_sir_destroy(filt), "mgp_sir_destroy")
 
 
+def mgp_prefix_workspace_size(n: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().mgp_prefix_workspace_size(n, ctypes.byref(out)), "mgp_prefix_workspace_size")
+    return out.value
+
+
+def mgp_resample_prefix(w_dev: int, n: int, method: int, seed: int, stream_id: int, ancestors_dev: int,
+                        stats_dev: int, workspace_dev: int, workspace_bytes: int, stream: int) -> None:
+    _check(lib().mgp_resample_prefix(w_dev, n, method, int(seed) & (2**64 - 1), stream_id, ancestors_dev,
+                                     stats_dev or None, workspace_dev, workspace_bytes, stream or None),
+           "mgp_resample_prefix")
+
+
 def mgp_probe_stream_read(buf_dev: int, nbytes: int, passes: int, blocks: int, sink_dev: int, stream: int) -> None:
     _check(lib().mgp_probe_stream_read(buf_dev, nbytes, passes, blocks, sink_dev, stream or None),
            "mgp_probe_stream_read")
@@ -562,6 +582,36 @@ class Resampler:
         _require_weights(w)
         if w.device != self.workspace.device:
             raise ValueError(f"weights are on {w.device}, the workspace on {self.workspace.device}")
+
+
+class PrefixResampler:
+    """Holds a workspace for mgp_resample_prefix (multinomial or systematic
+    resampling, Algorithms 7 and 8) up to n_max particles."""
+
+    def __init__(self, n_max: int, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.ws_bytes = mgp_prefix_workspace_size(max(1, n_max))
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=self.device)
+
+    def resample(self, w, method="systematic", seed: int = 0, stream_id: int = 0, out=None,
+                 stream: int | None = None):
+        torch = _torch()
+        _require_weights(w)
+        if w.device != self.workspace.device:
+            raise ValueError(f"weights are on {w.device}, the workspace on {self.workspace.device}")
+        n = w.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=w.device)
+        _require_buffer(out, n, torch.int32, "out (ancestors)", w.device)
+        m = PREFIX_METHODS[method] if isinstance(method, str) else int(method)
+        mgp_resample_prefix(w.data_ptr(), n, m, seed, stream_id, out.data_ptr(), self.stats.data_ptr(),
+                            self.workspace.data_ptr(), self.ws_bytes, current_stream() if stream is None else stream)
+        return out
+
+    def last_stats(self) -> dict:
+        return decode_stats(self.stats)
 
 
 def resample(w, variant="megopolis", B: int = 0, epsilon: float = 0.01, seed: int = 0, stream_id: int = 0,

@@ -95,6 +95,13 @@ def test_argument_errors_before_any_device_call(mgp):
         mgp.mgp_resample_gather_prepared(16, 10, mgp.make_params(B=3), 256, 0, 0, 4096, 0, 0, 0)
     assert e.value.code == mgp.MGP_EINVAL
     assert "d must be" in mgp.mgp_last_error()
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_prefix_workspace_size(0)
+    assert e.value.code == mgp.MGP_EINVAL
+    with pytest.raises(mgp.MgpError) as e:  # unknown method, before any device call
+        mgp.mgp_resample_prefix(16, 10, 5, 1, 0, 16, 0, 256, 1 << 20, 0)
+    assert e.value.code == mgp.MGP_EINVAL
+    assert mgp.mgp_prefix_workspace_size(1 << 20) >= 8 << 20
 
 
 def test_noalloc_size_limit_checked_on_the_host(mgp):
