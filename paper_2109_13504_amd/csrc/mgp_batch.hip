@@ -139,12 +139,16 @@ __device__ __forceinline__ void process_tile(const FilterDev& F, const mgp_stats
             }
         }
     } else {
+        // every lane runs a chain (lanes past n as n - 1, whose group is that
+        // of the real lanes of its half-wave: tiles start on multiples of 64),
+        // so that C2 shares each group's partition draws across the half-wave
         const LoopParams L{F.w, F.offsets, n, B, F.key0, F.key1, F.stream_id, F.n_w, F.n_part};
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const uint32_t i = start + threadIdx.x + BT * p;
+            const uint32_t ic = i < n ? i : n - 1u;
+            const uint32_t k = run_chain<V, true, true>(L, ic);
             if (i < n) {
-                const uint32_t k = run_chain<V, true>(L, i);
                 F.anc[i] = (int32_t)k;
                 gather_row(F, i, (int32_t)k, d);
             }

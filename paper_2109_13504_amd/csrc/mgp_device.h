@@ -183,7 +183,14 @@ struct Unroll {
 // input position pos (i itself when inputs and outputs are the same
 // particles, i mod n for M != N resampling): the Megopolis segment
 // arithmetic uses pos, the random draws and the C1/C2 group use i.
-template <int V, bool Narrow>
+// Shared (C2 only): every lane of the wave runs a chain, and the 32 lanes of
+// each half-wave hold the 32 particles of one group (i - lane a multiple of
+// 32 within the half-wave). The group's partition draw of each step is the
+// same for its 32 particles, so instead of each lane calling the generator
+// once per four steps, lane k of the half-wave makes the call of the k-th
+// four-step block of the next twenty steps and the others read its words
+// with a cross-lane permute: one call per lane per twenty steps.
+template <int V, bool Narrow, bool Shared = false>
 __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, uint32_t pos)
 {
     const float* __restrict__ w = P.w;
@@ -200,12 +207,20 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
     }
 
     constexpr uint32_t U = Unroll<V>::value;
+    constexpr bool kShare = Shared && V == kC2;
     const uint32_t nblk = P.B / U;
+    // Shared: the lane of the half-wave that made block k's call
+    const uint32_t half_base = (__lane_id() & 32u);
     for (uint32_t q = 0; q < nblk; ++q) {
         UBlock ub;
-        Words jb{}, pb{};
+        Words jb{}, pb{}, pmine{};
         uint32_t jj[U];
         float wj[U];
+        if constexpr (kShare) {
+            // lane k (< U / 4) of the half-wave: the call of block q U / 4 + k
+            const uint32_t k = __lane_id() & 31u;
+            pmine = philox(q * (U / 4) + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, group, P.key0, P.key1);
+        }
         // candidates and their weights first: they do not depend on k
 #pragma unroll
         for (uint32_t s = 0; s < U; ++s) {
@@ -217,7 +232,7 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
                 if (s % 4 == 0) {
                     const uint32_t blk = q * (U / 4) + s / 4;
                     jb = philox(blk, kTagJ, P.stream_id, i, P.key0, P.key1);
-                    if constexpr (V == kC2) pb = philox(blk, kTagC2Part, P.stream_id, group, P.key0, P.key1);
+                    if constexpr (V == kC2 && !kShare) pb = philox(blk, kTagC2Part, P.stream_id, group, P.key0, P.key1);
                 }
                 const uint32_t jw = word(jb, s % 4);
                 if constexpr (V == kMetropolis) {
@@ -225,7 +240,12 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
                 } else if constexpr (V == kC1) {
                     j = partition_index(c1_part, jw, P.n, P.n_w);
                 } else {
-                    j = partition_index(uniform_index(word(pb, s % 4), P.n_part), jw, P.n, P.n_w);
+                    uint32_t pw;
+                    if constexpr (kShare)
+                        pw = (uint32_t)__shfl((int)word(pmine, s % 4), (int)(half_base + s / 4), 64);
+                    else
+                        pw = word(pb, s % 4);
+                    j = partition_index(uniform_index(pw, P.n_part), jw, P.n, P.n_w);
                 }
             }
             jj[s] = j;
@@ -279,10 +299,10 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
     return k;
 }
 
-template <int V, bool Narrow>
+template <int V, bool Narrow, bool Shared = false>
 __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i)
 {
-    return run_chain<V, Narrow>(P, i, i);
+    return run_chain<V, Narrow, Shared>(P, i, i);
 }
 
 // ---------------------------------------------------------------------------

@@ -96,14 +96,16 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample(const float* __restri
     // the stats must come from the reduction of this very call (same n,
     // variant, seed and stream), and B must fit the workspace
     const bool ok = st->status == MGP_OK && st->tag == tag && st->n == n && B <= b_cap;
-    if (i >= m) return;
     int32_t k = -1;
     if (ok) {
+        // every lane runs a chain, also past m (C2 shares each group's
+        // partition draws across its half-wave): output i starts at input
+        // i mod n, i itself when i < n
         LoopParams P{w, offsets, n, B, key0, key1, stream_id, n_w, n_part, seg_mask};
-        // output i starts at input i mod n (i itself when m <= n)
         const uint32_t pos = i < n ? i : i % n;
-        k = (int32_t)run_chain<V, Narrow>(P, i, pos);
+        k = (int32_t)run_chain<V, Narrow, true>(P, i, pos);
     }
+    if (i >= m) return;
     if (anc) anc[i] = k;
     if (rc.states) copy_row(rc, i, k);
 }
@@ -495,12 +497,15 @@ __global__ __launch_bounds__(kLoopThreads) void k_resample_small(const float* __
     __shared__ mgp_stats st_local;
     const uint32_t B = small_prologue(w, n, nparts, chunk, copy_vec, fold_vec, a, st_ws, st_user, M, parts, &st_local);
     const uint32_t i = blockIdx.x * kLoopThreads + threadIdx.x;
-    if (i >= n) return;
     int32_t k = -1;  // invalid weights: B == 0
     if (B > 0) {
+        // every lane runs a chain (lanes past n from n - 1's group, whose
+        // partition draws C2 shares across the half-wave)
         const LoopParams P{M, nullptr, n, B, a.key0, a.key1, a.stream_id, n_w, n_part};
-        k = (int32_t)run_chain<V, true>(P, i, i);
+        const uint32_t ic = i < n ? i : n - 1u;
+        k = (int32_t)run_chain<V, true, true>(P, ic, ic);
     }
+    if (i >= n) return;
     if (anc) anc[i] = k;
     if (rc.states) copy_row(rc, i, k);
 }
