@@ -132,6 +132,27 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
+def median_call_ms(torch, fn, runs=10, warmup=3):
+    """Median device time (HIP events on the current stream) of fn(k) for k =
+    warmup .. warmup + runs - 1, after `warmup` untimed calls (fn(0) ..) that
+    bring the weights into the caches and the launch path up to speed. Each
+    timed call is synchronised alone."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        fn(k)
+    torch.cuda.synchronize()
+    times = []
+    for k in range(warmup, warmup + runs):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn(k)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
 def cpu_baseline(w_np, variant, eps, stride):
     """The oracle as it is, single-threaded, on a bounded sample: the full
     reduction and B, then the chains of every stride-th particle."""
@@ -280,7 +301,8 @@ def batched_section(torch, mgp, inputs, runs, shape=None):
 def sweep_section(torch, mgp, inputs):
     """The paper's timing experiment on this GPU: resample time (reduction, B,
     accept loop; no gather) at N = 2^22 for Megopolis, Metropolis, C1 and C2
-    at 128 and 2048 bytes, y = 0..4, eps = 0.01; median of 5 runs. Then the
+    at 128 and 2048 bytes, y = 0..4, eps = 0.01; median of 10 calls after 3
+    warm-up calls. Then the
     partition-size study: C1 and C2 at 128..2048 bytes at y = 4."""
     import numpy as np
     dev = torch.device("cuda:0")
@@ -294,39 +316,23 @@ def sweep_section(torch, mgp, inputs):
         w = torch.from_numpy(inputs.gaussian_weights(n, float(y), 0)).to(dev)
         for v, ps in rows:
             key = f"{v}-ps{ps}" if v in ("c1", "c2") else v
-            times = []
-            for k in range(6):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                r.resample(w, v, epsilon=0.01, seed=k, partition_bytes=ps, out=anc)
-                b.record(stream)
-                torch.cuda.synchronize()
-                if k:
-                    times.append(a.elapsed_time(b))
-            out.setdefault(key, {})[f"y{y}"] = {"ms": float(np.median(times)), "B": r.last_stats()["B"]}
+            ms = median_call_ms(torch, lambda k: r.resample(w, v, epsilon=0.01, seed=k, partition_bytes=ps, out=anc))
+            out.setdefault(key, {})[f"y{y}"] = {"ms": ms, "B": r.last_stats()["B"]}
     # the partition-size study: C1 and C2 at every partition size, y = 4
     w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
     parts = {}
     for v in ("c1", "c2"):
         for ps in (128, 256, 512, 1024, 2048):
-            times = []
-            for k in range(6):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                r.resample(w, v, epsilon=0.01, seed=k, partition_bytes=ps, out=anc)
-                b.record(stream)
-                torch.cuda.synchronize()
-                if k:
-                    times.append(a.elapsed_time(b))
-            parts[f"{v}-ps{ps}"] = float(np.median(times))
+            parts[f"{v}-ps{ps}"] = median_call_ms(
+                torch, lambda k: r.resample(w, v, epsilon=0.01, seed=k, partition_bytes=ps, out=anc))
     return {"workload": "N=2^22, Gaussian-likelihood weights, eps=0.01; resample = reduction + B + accept loop "
-                        "(no gather); median of 5 runs", "ms": out,
+                        "(no gather); median of 10 calls after 3 warm-up calls", "ms": out,
             "partition_sizes_y4_ms": parts}
 
 
 def configs_section(torch, mgp, inputs):
     """The two smaller workloads, timed like the paper's experiment (median of
-    the runs after one warm-up, HIP events on the launch stream):
+    the calls after 3 warm-up calls, HIP events on the launch stream):
       - one filter, N = 4096, y = 2, eps = 0.01: Metropolis and Megopolis,
         resample only (reduction + B + accept loop);
       - one filter, N = 2^20, y = 0..4, eps = 0.01: the four variants (C1/C2
@@ -337,16 +343,7 @@ def configs_section(torch, mgp, inputs):
     stream = torch.cuda.current_stream()
 
     def med(fn, runs):
-        times = []
-        for k in range(runs + 1):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            fn(k)
-            b.record(stream)
-            torch.cuda.synchronize()
-            if k:
-                times.append(a.elapsed_time(b))
-        return float(np.median(times))
+        return median_call_ms(torch, fn, runs=runs)
 
     small = {}
     n = 4096
@@ -365,17 +362,18 @@ def configs_section(torch, mgp, inputs):
         wn, st = inputs.gaussian_weights_and_states(n, float(y), 4, 0)
         w, states = torch.from_numpy(wn).to(dev), torch.from_numpy(st).to(dev)
         for v in ("megopolis", "metropolis", "c1", "c2"):
-            ms_r = med(lambda k: r.resample(w, v, epsilon=0.01, seed=k, out=anc), 5)
+            ms_r = med(lambda k: r.resample(w, v, epsilon=0.01, seed=k, out=anc), 10)
             B = r.last_stats()["B"]
 
             def step(k):
                 r.resample(w, v, epsilon=0.01, seed=k, out=anc)
                 mgp.gather(states, anc, out=out)
-            mid.setdefault(v, {})[f"y{y}"] = {"resample_ms": ms_r, "with_gather_ms": med(step, 5), "B": B}
+            mid.setdefault(v, {})[f"y{y}"] = {"resample_ms": ms_r, "with_gather_ms": med(step, 10), "B": B}
     return {"n4096_y2": {"workload": "single filter, N=4096, y=2, eps=0.01; resample = reduction + B + accept loop; "
-                                     "median of 20 runs", "ms": small},
+                                     "median of 20 calls after 3 warm-up calls", "ms": small},
             "n2pow20": {"workload": "single filter, N=2^20, y=0..4, eps=0.01, C1/C2 at 128-byte partitions; "
-                                    "resample, and resample + gather of D=4 fp32 states; median of 5 runs",
+                                    "resample, and resample + gather of D=4 fp32 states; median of 10 calls after 3 "
+                                    "warm-up calls",
                         "ms": mid}}
 
 
@@ -475,7 +473,8 @@ K40M_MEGOPOLIS_Y4 = {1 << 15: 5.170e-4, 1 << 16: 8.173e-4, 1 << 17: 0.0014, 1 <<
 def n_sweep_section(torch, mgp, inputs):
     """Megopolis resample time (reduction, B, offsets, accept loop; no
     gather) against N = 2^12 .. 2^26, Gaussian-likelihood weights y = 4,
-    eps = 0.01, median of 5; the paper's Table 3 y = 4 column (from 2^15) as
+    eps = 0.01, median of 10 calls after 3 warm-up calls; the paper's Table 3
+    y = 4 column (from 2^15) as
     context."""
     import numpy as np
     dev = torch.device("cuda:0")
@@ -486,16 +485,7 @@ def n_sweep_section(torch, mgp, inputs):
         w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
         anc = torch.empty(n, dtype=torch.int32, device=dev)
         r = mgp.Resampler(n)
-        times = []
-        for k in range(6):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            r.resample(w, "megopolis", epsilon=0.01, seed=k, out=anc)
-            b.record(stream)
-            torch.cuda.synchronize()
-            if k:
-                times.append(a.elapsed_time(b))
-        ms = float(np.median(times))
+        ms = median_call_ms(torch, lambda k: r.resample(w, "megopolis", epsilon=0.01, seed=k, out=anc))
         B = r.last_stats()["B"]
         k40 = K40M_MEGOPOLIS_Y4.get(n)
         rows[f"2^{ln}"] = {"ms": ms, "B": B, "particles_per_s": n / (ms * 1e-3),
@@ -503,7 +493,7 @@ def n_sweep_section(torch, mgp, inputs):
                            "k40m_ms": k40 * 1e3 if k40 else None}
         del w, anc, r
     return {"workload": "Megopolis, Gaussian-likelihood weights y=4, eps=0.01; resample = reduction + B + accept loop "
-                        "(no gather); median of 5; k40m_ms from Table 3", "rows": rows}
+                        "(no gather); median of 10 after 3 warm-up calls; k40m_ms from Table 3", "rows": rows}
 
 
 def prefix_section(torch, mgp, inputs):
@@ -511,23 +501,15 @@ def prefix_section(torch, mgp, inputs):
     GPU: multinomial (Algorithm 7) and systematic (Algorithm 8) resampling
     through mgp_resample_prefix against Megopolis (mgp_resample), N = 2^16 ..
     2^24, y = 0, 2, 4, eps = 0.01; each a whole call (reduction and validation,
-    the fixed-point prefix sum, the search), median of 5 after one warm-up."""
+    the fixed-point prefix sum, the search), median of 10 calls after 3
+    warm-up calls."""
     import numpy as np
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     out = {}
 
     def med(fn):
-        times = []
-        for k in range(6):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            fn(k)
-            b.record(stream)
-            torch.cuda.synchronize()
-            if k:
-                times.append(a.elapsed_time(b))
-        return float(np.median(times))
+        return median_call_ms(torch, fn)
 
     for ln in (16, 20, 24):
         n = 1 << ln
@@ -550,14 +532,14 @@ def prefix_section(torch, mgp, inputs):
         f"{k} mult {v['multinomial_ms']:.3f} syst {v['systematic_ms']:.3f} mego {v['megopolis_ms']:.3f} ms"
         for k, v in out.items()))
     return {"workload": "Gaussian-likelihood weights, eps=0.01 for Megopolis; whole resample calls, ancestors only, "
-                        "median of 5", "rows": out}
+                        "median of 10 after 3 warm-up calls", "rows": out}
 
 
 def m_neq_n_section(torch, mgp, inputs):
     """M != N resampling (Section 8's D-PMC remark): Megopolis, B from
     eps = 0.01 on Gaussian-likelihood weights with y = 4, N inputs -> M
     outputs for (2^24 -> 2^22) and (2^22 -> 2^24); whole mgp_resample_m call
-    (reduction, B, offsets, accept loop), median of 5."""
+    (reduction, B, offsets, accept loop), median of 10 after 3 warm-up calls."""
     import numpy as np
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -567,17 +549,8 @@ def m_neq_n_section(torch, mgp, inputs):
         w = torch.from_numpy(inputs.gaussian_weights(n, 4.0, 0)).to(dev)
         anc = torch.empty(m, dtype=torch.int32, device=dev)
         r = mgp.Resampler(n)
-        times = []
-        for k in range(6):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            r.resample_m(w, m, "megopolis", epsilon=0.01, seed=k, out=anc)
-            b.record(stream)
-            torch.cuda.synchronize()
-            if k:
-                times.append(a.elapsed_time(b))
+        ms = median_call_ms(torch, lambda k: r.resample_m(w, m, "megopolis", epsilon=0.01, seed=k, out=anc))
         B = r.last_stats()["B"]
-        ms = float(np.median(times))
         out[f"n2^{ln}_m2^{lm}"] = {"ms": ms, "B": B, "outputs_per_s": m / (ms * 1e-3),
                                    "kernel": "mirrored" if m <= n else "generic",
                                    "effective_GBs": 4.0 * m * (B + 2) / (ms * 1e-3) / 1e9}

@@ -497,7 +497,9 @@ __device__ __forceinline__ void store_stream(float4* p, const float4& v)
     __builtin_nontemporal_store(v.w, &p->w);
 }
 
-// Output row i from input row k, one lane, any d.
+// Output row i from input row k, one lane, any d: up to four vectors (or
+// four floats) loaded before the first of them is stored, so a row of up to
+// 16 floats costs one round trip.
 __device__ __forceinline__ void copy_row(const RowCopy& g, uint32_t i, int32_t k)
 {
     const float4 nan4 = make_float4(NAN, NAN, NAN, NAN);
@@ -506,19 +508,27 @@ __device__ __forceinline__ void copy_row(const RowCopy& g, uint32_t i, int32_t k
         const uint32_t d4 = g.d >> 2;
         const float4* src = reinterpret_cast<const float4*>(g.states) + kr * d4;
         float4* dst = reinterpret_cast<float4*>(g.out) + (uint64_t)i * d4;
-        uint32_t c = 0;
-        for (; c + 4u <= d4; c += 4u) {  // four loads in flight before the stores
+        for (uint32_t c = 0; c < d4; c += 4u) {
             float4 v[4];
 #pragma unroll
-            for (uint32_t u = 0; u < 4u; ++u) v[u] = k < 0 ? nan4 : src[c + u];
+            for (uint32_t u = 0; u < 4u; ++u)
+                if (c + u < d4) v[u] = k < 0 ? nan4 : src[c + u];
 #pragma unroll
-            for (uint32_t u = 0; u < 4u; ++u) store_stream(dst + c + u, v[u]);
+            for (uint32_t u = 0; u < 4u; ++u)
+                if (c + u < d4) store_stream(dst + c + u, v[u]);
         }
-        for (; c < d4; ++c) store_stream(dst + c, k < 0 ? nan4 : src[c]);
     } else {
         const float* src = g.states + kr * g.d;
         float* dst = g.out + (uint64_t)i * g.d;
-        for (uint32_t c = 0; c < g.d; ++c) __builtin_nontemporal_store(k < 0 ? NAN : src[c], dst + c);
+        for (uint32_t c = 0; c < g.d; c += 4u) {
+            float v[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u)
+                if (c + u < g.d) v[u] = k < 0 ? NAN : src[c + u];
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u)
+                if (c + u < g.d) __builtin_nontemporal_store(v[u], dst + c + u);
+        }
     }
 }
 
