@@ -411,8 +411,13 @@ def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20,
     x0 = inputs.sir_initial_particles_torch(R, n, dev)
     stream = torch.cuda.current_stream()
     out = {}
+    unbiased = {r["method"]: (r["resample_ratio"], r["rmse"])
+                for r in json.load(open(os.path.join(ROOT, "tests", "golden", "sir_table2.json")))["unbiased"]}
     for variant, B in rows:
-        key = f"{variant}-B{B}" if variant not in ("c1", "c2") else f"{variant}-ps128-B{B}"
+        if variant in unbiased:
+            key = variant
+        else:
+            key = f"{variant}-B{B}" if variant not in ("c1", "c2") else f"{variant}-ps128-B{B}"
         t0 = time.perf_counter()
         f = mgp.SirFilter(R, n, T, variant=variant, B=B, epsilon=0.1, seed=2021, use_graph=True)
         create_s = time.perf_counter() - t0
@@ -444,7 +449,7 @@ def sir_section(torch, mgp, inputs, rows, trajectories=16, mc_runs=50, log2n=20,
         f.close()
         rmse, per_traj = sir_rmse(est, truth, trajectories, mc_runs)
         ratio = tau[1] / sum(tau)
-        paper = table2().get((variant, B))
+        paper = unbiased.get(variant) if variant in unbiased else table2().get((variant, B))
         steps = R * n * T
         out[key] = {
             "B": B, "rmse": rmse, "rmse_per_trajectory_min": float(per_traj.min()),
@@ -820,6 +825,7 @@ def main():
         rows = [("megopolis", 16)]
         if args.sir_table:
             rows = [(v, b) for b in (16, 32, 64) for v in ("megopolis", "metropolis", "c1", "c2")]
+            rows += [("multinomial", 0), ("systematic", 0)]  # Table 2's unbiased rows (Algorithms 7 and 8)
         if args.sir_bsweep:
             rows = [(v, b) for b in (5, 7, 10, 15, 20, 25, 30, 40) for v in ("megopolis", "metropolis", "c1", "c2")]
             rows.append(("megopolis", 0))  # B from eq. (bcalc) with epsilon = 0.1 at every step

@@ -393,8 +393,15 @@ int mgp_server_destroy(mgp_server* server);
  * x_bar_t = x_t and its estimate is their mean. Results are pure functions of (x_bar_0, z, config): identical for
  * every launch shape and for graph or stage-by-stage execution, up to the
  * ~1e-16 relative rounding order of the fp64 mean. */
+/* Stage 2 by a prefix-sum method (the unbiased comparison rows of Table 2):
+ * values of mgp_sir_config.variant beside the mgp_variant ones. B, epsilon,
+ * partition_bytes, block_threads and particles_per_thread are then unused
+ * (the B history records 1). */
+#define MGP_SIR_MULTINOMIAL 4 /* Algorithm 7 */
+#define MGP_SIR_SYSTEMATIC 5  /* Algorithm 8 */
+
 typedef struct mgp_sir_config {
-    int32_t variant;              /* mgp_variant of stage 2 */
+    int32_t variant;              /* mgp_variant of stage 2, or MGP_SIR_MULTINOMIAL / MGP_SIR_SYSTEMATIC */
     int32_t runs;                 /* R, 1 <= R <= 65535 (e.g. trajectories x Monte Carlo runs) */
     int32_t n;                    /* particles per run, 1 <= n <= 2^29 - 4096, R * n <= 2^32 */
     int32_t steps;                /* T >= 1: the filter runs steps t = 1..T */

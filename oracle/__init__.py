@@ -297,7 +297,9 @@ def sir_filter(x0: np.ndarray, z: np.ndarray, variant, B: int, seed: int, run: i
       stage 1: predict + update (sir_predict_update);
       stage 2: resample with B iterations (B = 0: B from eq. (bcalc) with
                `epsilon`, per step), Philox key sir_step_seed(seed, t), stream
-               `run`, then x_bar = x[ancestors];
+               `run`, then x_bar = x[ancestors]; variant "multinomial" or
+               "systematic" resamples by resample_prefix instead (B recorded
+               as 1);
       stage 3: the estimate, the mean of x_bar.
     A step whose weights are all zero (fp32 underflow) keeps the predicted
     particles unresampled (x_bar = x) and reports MGP_EWEIGHTS.
@@ -310,6 +312,11 @@ def sir_filter(x0: np.ndarray, z: np.ndarray, variant, B: int, seed: int, run: i
         st = reduce(w)
         if st.status:
             xbar, b = x, 0
+        elif isinstance(variant, str) and variant in PREFIX_METHODS:
+            # stage 2 by a prefix-sum method (Algorithms 7 and 8): no iterations
+            b = 1
+            anc = resample_prefix(w, variant, sir_step_seed(seed, t), stream_id=run)
+            xbar = gather(x, anc).reshape(-1)
         else:
             b = B if B > 0 else choose_B(st.w_sum, st.w_max, w.size, epsilon)[0]
             anc = resample(w, variant, b, sir_step_seed(seed, t), stream_id=run, partition_bytes=partition_bytes)

@@ -69,6 +69,11 @@ int enqueue_batch(int variant, const LoopShape& sh, const FilterDev* d_fd, uint3
                   uint32_t n_rt, Partial* d_parts, mgp_stats* d_stats, const LTile* d_lt, uint32_t grid,
                   const uint32_t* d_qoff, uint32_t* d_qcount, uint32_t nxcd, uint32_t d, hipStream_t s);
 
+// The finalize step alone (one block per filter: the stats record, B, and
+// for Megopolis the offsets) over partials already written.
+int enqueue_batch_finalize(const FilterDev* d_fd, uint32_t count, Partial* d_parts, mgp_stats* d_stats,
+                           uint32_t* d_qcount, hipStream_t s);
+
 bool batch_shape_supported(int variant, const LoopShape& sh);
 
 }  // namespace mgp

@@ -189,7 +189,8 @@ struct Unroll {
 // same for its 32 particles, so instead of each lane calling the generator
 // once per four steps, lane k of the half-wave makes the call of the k-th
 // four-step block of the next twenty steps and the others read its words
-// with a cross-lane permute: one call per lane per twenty steps.
+// with a cross-lane permute: one call per lane per twenty steps (and one for
+// the B mod 20 steps of the tail).
 template <int V, bool Narrow, bool Shared = false>
 __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, uint32_t pos)
 {
@@ -209,8 +210,6 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
     constexpr uint32_t U = Unroll<V>::value;
     constexpr bool kShare = Shared && V == kC2;
     const uint32_t nblk = P.B / U;
-    // Shared: the lane of the half-wave that made block k's call
-    const uint32_t half_base = (__lane_id() & 32u);
     for (uint32_t q = 0; q < nblk; ++q) {
         UBlock ub;
         Words jb{}, pb{}, pmine{};
@@ -242,7 +241,7 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
                 } else {
                     uint32_t pw;
                     if constexpr (kShare)
-                        pw = (uint32_t)__shfl((int)word(pmine, s % 4), (int)(half_base + s / 4), 64);
+                        pw = (uint32_t)__shfl((int)word(pmine, s % 4), (int)((__lane_id() & 32u) + s / 4), 64);
                     else
                         pw = word(pb, s % 4);
                     j = partition_index(uniform_index(pw, P.n_part), jw, P.n, P.n_w);
@@ -267,7 +266,16 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
     // or of 5 for Megopolis, which draws no j)
     UBlock ub{};
     Words jb{}, pb{};
-    for (uint32_t b = nblk * U; b < P.B; ++b) {
+    const uint32_t b0 = nblk * U;
+    if constexpr (kShare) {
+        // the tail needs at most U / 4 partition blocks, from block b0 / 4 on:
+        // lane k (< U / 4) of the half-wave makes the call of block b0 / 4 + k
+        if (b0 < P.B) {
+            const uint32_t k = __lane_id() & 31u;
+            pb = philox(b0 / 4u + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, group, P.key0, P.key1);
+        }
+    }
+    for (uint32_t b = b0; b < P.B; ++b) {
         const uint32_t r5 = b % 5u;
         const uint32_t r4 = b % 4u;
         if (r5 == 0u) ub = u_block(philox(b / 5u, kTagU, P.stream_id, i, P.key0, P.key1));
@@ -277,7 +285,7 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
         } else {
             if (r4 == 0u) {
                 jb = philox(b / 4u, kTagJ, P.stream_id, i, P.key0, P.key1);
-                if constexpr (V == kC2) pb = philox(b / 4u, kTagC2Part, P.stream_id, group, P.key0, P.key1);
+                if constexpr (V == kC2 && !kShare) pb = philox(b / 4u, kTagC2Part, P.stream_id, group, P.key0, P.key1);
             }
             const uint32_t jw = word(jb, r4);
             if constexpr (V == kMetropolis) {
@@ -285,7 +293,12 @@ __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, u
             } else if constexpr (V == kC1) {
                 j = partition_index(c1_part, jw, P.n, P.n_w);
             } else {
-                j = partition_index(uniform_index(word(pb, r4), P.n_part), jw, P.n, P.n_w);
+                uint32_t pw;
+                if constexpr (kShare)
+                    pw = (uint32_t)__shfl((int)word(pb, r4), (int)((__lane_id() & 32u) + (b - b0) / 4u), 64);
+                else
+                    pw = word(pb, r4);
+                j = partition_index(uniform_index(pw, P.n_part), jw, P.n, P.n_w);
             }
         }
         const float wjv = load_weight<Narrow>(w, j);

@@ -34,6 +34,7 @@
 #include "mgp.h"
 #include "mgp_device.h"
 #include "mgp_internal.h"
+#include "mgp_prefix.h"
 
 namespace mgp {
 
@@ -41,7 +42,6 @@ constexpr uint32_t kPrefixThreads = 256;
 constexpr uint32_t kPrefixPer = 8;                        // weights per thread in a chunk
 constexpr uint32_t kChunk = kPrefixThreads * kPrefixPer;  // 2048 weights per chunk
 constexpr uint32_t kFan = 16;                             // the tree's fan-out: one 128-byte row of sums
-constexpr int kMaxLevels = 8;                             // 16^8 = 2^32 > any n
 constexpr uint32_t kTagMultinomial = 6u;
 constexpr uint32_t kTagSystematic = 7u;
 
@@ -52,13 +52,11 @@ struct PrefixHeader {
     int32_t valid;   // 1 when the weights passed validation
 };
 
-// The tree above level 0: level k (1..top) at t[k], with count[k] real
-// entries (the last is S), padded with S to a multiple of kFan.
-struct Tree {
-    uint64_t* t[kMaxLevels + 1];
-    uint32_t count[kMaxLevels + 1];
-    int top;  // 0 when n <= kFan (level 0 alone)
-};
+template <typename T>
+__device__ __forceinline__ T* at(const PrefixJob& J, uint64_t off)
+{
+    return reinterpret_cast<T*>(J.region + (uint64_t)blockIdx.y * J.region_ld + off);
+}
 
 // K = 62 - ceil(log2 n) - E for w_max = m 2^E, m in [0.5, 1).
 __device__ __forceinline__ int fixed_exponent(float w_max, int log2n_ceil)
@@ -109,12 +107,12 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* t
 }
 
 // The fixed-point weights of this thread's kPrefixPer consecutive inputs of
-// chunk `chunk` (0 past n). vec: w 16-byte aligned (n may be ragged).
-__device__ __forceinline__ void load_fixed(const float* __restrict__ w, uint32_t n, uint32_t chunk, int K, bool vec,
-                                           uint64_t (&q)[kPrefixPer])
+// chunk `chunk` of the run (0 past n).
+__device__ __forceinline__ void load_fixed(const PrefixJob& J, uint32_t chunk, int K, uint64_t (&q)[kPrefixPer])
 {
+    const float* __restrict__ w = J.w + (uint64_t)blockIdx.y * J.w_ld;
     const uint64_t base = (uint64_t)chunk * kChunk + (uint64_t)threadIdx.x * kPrefixPer;
-    if (vec && base + kPrefixPer <= n) {
+    if (J.vec && base + kPrefixPer <= J.n) {
         const float4 a = *reinterpret_cast<const float4*>(w + base);
         const float4 b = *reinterpret_cast<const float4*>(w + base + 4);
         const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
@@ -122,21 +120,20 @@ __device__ __forceinline__ void load_fixed(const float* __restrict__ w, uint32_t
         for (uint32_t e = 0; e < kPrefixPer; ++e) q[e] = fixed_weight(v[e], K);
     } else {
 #pragma unroll
-        for (uint32_t e = 0; e < kPrefixPer; ++e) q[e] = base + e < n ? fixed_weight(w[base + e], K) : 0u;
+        for (uint32_t e = 0; e < kPrefixPer; ++e) q[e] = base + e < J.n ? fixed_weight(w[base + e], K) : 0u;
     }
 }
 
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_chunks(const float* __restrict__ w, uint32_t n,
-                                                                  int log2n_ceil, uint32_t vec,
-                                                                  const mgp_stats* __restrict__ st,
-                                                                  uint64_t* __restrict__ chunk_sum)
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_chunks(PrefixJob J)
 {
-    if (st->status != MGP_OK) {
+    const mgp_stats& st = J.stats[blockIdx.y];
+    uint64_t* chunk_sum = at<uint64_t>(J, J.o_sum);
+    if (st.status != MGP_OK) {
         if (threadIdx.x == 0) chunk_sum[blockIdx.x] = 0;
         return;
     }
     uint64_t q[kPrefixPer];
-    load_fixed(w, n, blockIdx.x, fixed_exponent(st->w_max, log2n_ceil), vec != 0u, q);
+    load_fixed(J, blockIdx.x, fixed_exponent(st.w_max, J.log2n), q);
     uint64_t s = 0;
 #pragma unroll
     for (uint32_t e = 0; e < kPrefixPer; ++e) s += q[e];
@@ -145,30 +142,30 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix_chunks(const float* _
     if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
 }
 
-// One block: chunk_excl[c] = sum of chunk_sum[0..c), and the header.
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_top(const uint64_t* __restrict__ chunk_sum, uint32_t nch,
-                                                               int log2n_ceil, const mgp_stats* __restrict__ st,
-                                                               uint64_t* __restrict__ chunk_excl,
-                                                               PrefixHeader* __restrict__ hdr)
+// One block per run: chunk_excl[c] = sum of chunk_sum[0..c), and the header.
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_top(PrefixJob J)
 {
+    const uint64_t* chunk_sum = at<uint64_t>(J, J.o_sum);
+    uint64_t* chunk_excl = at<uint64_t>(J, J.o_excl);
     // thread t owns chunks [t * per, (t + 1) * per)
-    const uint32_t per = (nch + kPrefixThreads - 1u) / kPrefixThreads;
+    const uint32_t per = (J.nch + kPrefixThreads - 1u) / kPrefixThreads;
     const uint32_t c0 = threadIdx.x * per;
     uint64_t s = 0;
-    for (uint32_t c = c0; c < c0 + per && c < nch; ++c) s += chunk_sum[c];
+    for (uint32_t c = c0; c < c0 + per && c < J.nch; ++c) s += chunk_sum[c];
     uint64_t total = 0;
     uint64_t run = block_exclusive_scan(s, &total);
-    for (uint32_t c = c0; c < c0 + per && c < nch; ++c) {
+    for (uint32_t c = c0; c < c0 + per && c < J.nch; ++c) {
         chunk_excl[c] = run;
         run += chunk_sum[c];
     }
     if (threadIdx.x == 0) {
-        const bool ok = st->status == MGP_OK;
+        const mgp_stats& st = J.stats[blockIdx.y];
+        const bool ok = st.status == MGP_OK;
         PrefixHeader h;
         h.total = ok ? total : 0u;
-        h.K = ok ? fixed_exponent(st->w_max, log2n_ceil) : 0;
+        h.K = ok ? fixed_exponent(st.w_max, J.log2n) : 0;
         h.valid = ok ? 1 : 0;
-        *hdr = h;
+        *at<PrefixHeader>(J, J.o_hdr) = h;
     }
 }
 
@@ -179,20 +176,18 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix_top(const uint64_t* _
 // level k entry m is the sum at position (m + 1) 16^k - 1, and the thread
 // holding position n - 1 writes the last real entry (S) and the padding of
 // every level.
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_scan(const float* __restrict__ w, uint32_t n, uint32_t vec,
-                                                                const PrefixHeader* __restrict__ hdr,
-                                                                const uint64_t* __restrict__ chunk_excl,
-                                                                uint64_t* __restrict__ incl, Tree tree)
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_scan(PrefixJob J)
 {
     __shared__ uint64_t stage[kChunk];
-    if (!hdr->valid) return;
+    const PrefixHeader h = *at<PrefixHeader>(J, J.o_hdr);
+    if (!h.valid) return;
     uint64_t q[kPrefixPer];
-    load_fixed(w, n, blockIdx.x, hdr->K, vec != 0u, q);
+    load_fixed(J, blockIdx.x, h.K, q);
     uint64_t s = 0;
 #pragma unroll
     for (uint32_t e = 0; e < kPrefixPer; ++e) s += q[e];
     uint64_t total = 0;
-    uint64_t run = chunk_excl[blockIdx.x] + block_exclusive_scan(s, &total);
+    uint64_t run = at<uint64_t>(J, J.o_excl)[blockIdx.x] + block_exclusive_scan(s, &total);
     const uint64_t base = (uint64_t)blockIdx.x * kChunk;
     const uint64_t mine = base + (uint64_t)threadIdx.x * kPrefixPer;
 #pragma unroll
@@ -200,35 +195,37 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix_scan(const float* __r
         run += q[e];
         stage[threadIdx.x * kPrefixPer + e] = run;
         const uint64_t p = mine + e;
-        if (p < n && (p + 1u) % kFan == 0u) {
+        if (p < J.n && (p + 1u) % kFan == 0u) {
             // level k entry (p + 1) / 16^k - 1 for every k with 16^k | p + 1
             uint64_t g = (p + 1u) / kFan;
-            for (int k = 1; k <= tree.top; ++k) {
-                tree.t[k][g - 1u] = run;
+            for (int k = 1; k <= J.top; ++k) {
+                at<uint64_t>(J, J.o_level[k])[g - 1u] = run;
                 if (g % kFan != 0u) break;
                 g /= kFan;
             }
         }
-        if (p == (uint64_t)n - 1u) {
-            for (int k = 1; k <= tree.top; ++k) {
-                const uint32_t end = (tree.count[k] + kFan - 1u) / kFan * kFan;
-                for (uint32_t m = tree.count[k] - 1u; m < end; ++m) tree.t[k][m] = run;
+        if (p == (uint64_t)J.n - 1u) {
+            for (int k = 1; k <= J.top; ++k) {
+                uint64_t* lv = at<uint64_t>(J, J.o_level[k]);
+                const uint32_t end = (J.count[k] + kFan - 1u) / kFan * kFan;
+                for (uint32_t m = J.count[k] - 1u; m < end; ++m) lv[m] = run;
             }
         }
     }
     __syncthreads();
+    uint64_t* incl = at<uint64_t>(J, J.o_incl);
 #pragma unroll
-    for (uint32_t e = 0; e < kPrefixPer; ++e) incl[base + e * kPrefixThreads + threadIdx.x] =
-        stage[e * kPrefixThreads + threadIdx.x];
+    for (uint32_t e = 0; e < kPrefixPer; ++e)
+        incl[base + e * kPrefixThreads + threadIdx.x] = stage[e * kPrefixThreads + threadIdx.x];
 }
 
 // The first j with incl[j] > t (t < S): down the tree, one row of kFan sums
 // per level.
-__device__ __forceinline__ uint32_t descend(uint64_t t, const Tree& tree, const uint64_t* __restrict__ incl)
+__device__ __forceinline__ uint32_t descend(const PrefixJob& J, uint64_t t)
 {
     uint64_t g = 0;
-    for (int k = tree.top; k >= 0; --k) {
-        const uint64_t* row = (k ? tree.t[k] : incl) + g * kFan;
+    for (int k = J.top; k >= 0; --k) {
+        const uint64_t* row = at<uint64_t>(J, k ? J.o_level[k] : J.o_incl) + g * kFan;
         uint64_t v[kFan];
 #pragma unroll
         for (uint32_t m = 0; m < kFan; m += 2) {
@@ -255,56 +252,62 @@ __device__ __forceinline__ uint32_t first_above(const uint64_t* __restrict__ a, 
     return lo;
 }
 
-// The threshold of output i in [0, S).
+// The threshold of output i of run r in [0, S).
 template <int Method>
-__device__ __forceinline__ uint64_t prefix_threshold(uint64_t S, uint32_t n, uint32_t i, uint32_t key0, uint32_t key1,
-                                                     uint32_t stream_id)
+__device__ __forceinline__ uint64_t prefix_threshold(const PrefixJob& J, uint64_t S, uint32_t i)
 {
+    const uint32_t sid = J.stream0 + blockIdx.y;
     if constexpr (Method == MGP_MULTINOMIAL) {
         // Algorithm 7: u ~ U[0, S), one 64-bit draw per output
-        const Words x = philox(0u, kTagMultinomial, stream_id, i, key0, key1);
+        const Words x = philox(0u, kTagMultinomial, sid, i, J.key0, J.key1);
         const uint64_t r = (uint64_t)x.x0 | ((uint64_t)x.x1 << 32);
         return __umul64hi(r, S);
     } else {
         // Algorithm 8: u = (i + u_t) / N after one draw u_t ~ U[0, 1), in fp64
         // with each operation rounded once
-        const Words x = philox(0u, kTagSystematic, stream_id, 0u, key0, key1);
+        const Words x = philox(0u, kTagSystematic, sid, 0u, J.key0, J.key1);
         const uint64_t r = (uint64_t)x.x0 | ((uint64_t)x.x1 << 32);
         const double ut = (double)(r >> 11) * 0x1p-53;
-        const double c = __ddiv_rn((double)S, (double)n);
+        const double c = __ddiv_rn((double)S, (double)J.n);
         const double v = __dmul_rn(__dadd_rn((double)i, ut), c);
         const uint64_t t = (uint64_t)floor(v);
         return t < S ? t : S - 1u;
     }
 }
 
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_multinomial(uint32_t n, const PrefixHeader* __restrict__ hdr,
-                                                                       Tree tree, const uint64_t* __restrict__ incl,
-                                                                       uint32_t key0, uint32_t key1,
-                                                                       uint32_t stream_id, int32_t* __restrict__ anc)
+// Output i of run r: the ancestor and, when the job copies rows, the row
+// (a NaN row for invalid weights, a = -1).
+__device__ __forceinline__ void emit(const PrefixJob& J, uint32_t i, int32_t a)
+{
+    const uint64_t r = blockIdx.y;
+    if (J.anc) J.anc[r * J.anc_ld + i] = a;
+    if (J.states) {
+        const RowCopy rc{J.states + r * J.rows_ld, J.out + r * J.rows_ld, J.d, J.vec4};
+        copy_row(rc, i, a);
+    }
+}
+
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_multinomial(PrefixJob J)
 {
     const uint32_t i = blockIdx.x * kPrefixThreads + threadIdx.x;
-    if (i >= n) return;
-    if (!hdr->valid) {
-        anc[i] = -1;
+    if (i >= J.n) return;
+    const PrefixHeader h = *at<PrefixHeader>(J, J.o_hdr);
+    if (!h.valid) {
+        emit(J, i, -1);
         return;
     }
-    const uint64_t t = prefix_threshold<MGP_MULTINOMIAL>(hdr->total, n, i, key0, key1, stream_id);
-    anc[i] = (int32_t)descend(t, tree, incl);
+    emit(J, i, (int32_t)descend(J, prefix_threshold<MGP_MULTINOMIAL>(J, h.total, i)));
 }
 
 // Systematic, first pass: the ancestors of outputs 0, G, 2G, ... (G =
 // kPrefixThreads) and n - 1, which bracket those of every output between.
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_brackets(uint32_t n, uint32_t nb,
-                                                                    const PrefixHeader* __restrict__ hdr, Tree tree,
-                                                                    const uint64_t* __restrict__ incl, uint32_t key0,
-                                                                    uint32_t key1, uint32_t stream_id,
-                                                                    uint32_t* __restrict__ bracket)
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_brackets(PrefixJob J, uint32_t nb)
 {
     const uint32_t b = blockIdx.x * kPrefixThreads + threadIdx.x;
-    if (b > nb || !hdr->valid) return;
-    const uint32_t i = b < nb ? b * kPrefixThreads : n - 1u;
-    bracket[b] = descend(prefix_threshold<MGP_SYSTEMATIC>(hdr->total, n, i, key0, key1, stream_id), tree, incl);
+    const PrefixHeader h = *at<PrefixHeader>(J, J.o_hdr);
+    if (b > nb || !h.valid) return;
+    const uint32_t i = b < nb ? b * kPrefixThreads : J.n - 1u;
+    at<uint32_t>(J, J.o_bracket)[b] = descend(J, prefix_threshold<MGP_SYSTEMATIC>(J, h.total, i));
 }
 
 // Systematic, second pass: output i's ancestor lies between the brackets of
@@ -314,70 +317,84 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix_brackets(uint32_t n, 
 // memory.
 constexpr uint32_t kStageMax = 2048;
 
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_systematic(uint32_t n, const PrefixHeader* __restrict__ hdr,
-                                                                      const uint32_t* __restrict__ bracket,
-                                                                      const uint64_t* __restrict__ incl,
-                                                                      uint32_t key0, uint32_t key1,
-                                                                      uint32_t stream_id, int32_t* __restrict__ anc)
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix_systematic(PrefixJob J)
 {
     __shared__ uint64_t stage[kStageMax];
     const uint32_t i = blockIdx.x * kPrefixThreads + threadIdx.x;
-    if (!hdr->valid) {
-        if (i < n) anc[i] = -1;
+    const PrefixHeader h = *at<PrefixHeader>(J, J.o_hdr);
+    if (!h.valid) {
+        if (i < J.n) emit(J, i, -1);
         return;
     }
+    const uint32_t* bracket = at<uint32_t>(J, J.o_bracket);
+    const uint64_t* incl = at<uint64_t>(J, J.o_incl);
     const uint32_t lo = bracket[blockIdx.x], hi = bracket[blockIdx.x + 1u];
     const uint32_t len = hi - lo + 1u;
-    const uint64_t t = prefix_threshold<MGP_SYSTEMATIC>(hdr->total, n, i < n ? i : n - 1u, key0, key1, stream_id);
+    const uint64_t t = prefix_threshold<MGP_SYSTEMATIC>(J, h.total, i < J.n ? i : J.n - 1u);
     if (len <= kStageMax) {  // the same for every lane of the block
         for (uint32_t k = threadIdx.x; k < len; k += kPrefixThreads) stage[k] = incl[lo + k];
         __syncthreads();
-        if (i < n) anc[i] = (int32_t)(lo + first_above(stage, 0u, len, t));
-    } else if (i < n) {
-        anc[i] = (int32_t)first_above(incl, lo, len, t);
+        if (i < J.n) emit(J, i, (int32_t)(lo + first_above(stage, 0u, len, t)));
+    } else if (i < J.n) {
+        emit(J, i, (int32_t)first_above(incl, lo, len, t));
     }
 }
 
-// Workspace layout after the reduction's region (stats, partials, one
-// offset): [header][chunk sums][chunk exclusive][brackets][tree levels
-// 1..top][level 0: the inclusive sums, whole chunks].
-static size_t align256(size_t b) { return (b + 255u) & ~(size_t)255u; }
+static uint64_t align256(uint64_t b) { return (b + 255u) & ~(uint64_t)255u; }
 
-struct PrefixLayout {
-    size_t hdr, chunk_sum, chunk_excl, bracket, level[kMaxLevels + 1], incl, total;
-    uint32_t count[kMaxLevels + 1];
-    int top;
-};
-
-static PrefixLayout prefix_layout(uint32_t n)
+// The layout of one run's scan region: [header][chunk sums][chunk exclusive
+// sums][brackets][tree levels 1..top][level 0: the inclusive sums, whole
+// chunks]. Returns the region's size.
+uint64_t prefix_region(uint32_t n, PrefixJob* J)
 {
-    const size_t nch = ((size_t)n + kChunk - 1u) / kChunk;
-    PrefixLayout L{};
-    L.hdr = workspace_bytes(1u);
-    L.chunk_sum = L.hdr + 256u;
-    L.chunk_excl = L.chunk_sum + align256(nch * 8u);
-    L.bracket = L.chunk_excl + align256(nch * 8u);
-    size_t at = L.bracket + align256(((size_t)n / kPrefixThreads + 2u) * 4u);
+    const uint64_t nch = ((uint64_t)n + kChunk - 1u) / kChunk;
+    uint64_t o = 0;
+    J->o_hdr = o;
+    o += 256u;
+    J->o_sum = o;
+    o += align256(nch * 8u);
+    J->o_excl = o;
+    o += align256(nch * 8u);
+    J->o_bracket = o;
+    o += align256(((uint64_t)n / kPrefixThreads + 2u) * 4u);
     // level k has ceil(n / 16^k) real entries; the top is the first with <= 16
     uint64_t cnt = n;
-    L.top = 0;
+    J->top = 0;
     while (cnt > kFan) {
         cnt = (cnt + kFan - 1u) / kFan;
-        ++L.top;
-        L.count[L.top] = (uint32_t)cnt;
-        L.level[L.top] = at;
-        at += align256((size_t)(cnt + kFan - 1u) / kFan * kFan * 8u);
+        ++J->top;
+        J->count[J->top] = (uint32_t)cnt;
+        J->o_level[J->top] = o;
+        o += align256((cnt + kFan - 1u) / kFan * kFan * 8u);
     }
-    L.incl = at;
-    L.total = L.incl + align256(nch * kChunk * 8u);
-    return L;
-}
-
-static int ceil_log2(uint32_t n)
-{
+    J->o_incl = o;
+    o += align256(nch * kChunk * 8u);
+    J->n = n;
+    J->nch = (uint32_t)nch;
     int L = 0;
     while (((uint64_t)1 << L) < (uint64_t)n) ++L;
-    return L;
+    J->log2n = L;
+    return o;
+}
+
+// Enqueues the scan and search of a job whose stats (validation, max) are
+// already on the device: R runs, method MGP_MULTINOMIAL or MGP_SYSTEMATIC.
+int enqueue_prefix(const PrefixJob& J, uint32_t R, int method, hipStream_t s)
+{
+    const dim3 chunks(J.nch, R);
+    hipLaunchKernelGGL(k_prefix_chunks, chunks, dim3(kPrefixThreads), 0, s, J);
+    hipLaunchKernelGGL(k_prefix_top, dim3(1, R), dim3(kPrefixThreads), 0, s, J);
+    hipLaunchKernelGGL(k_prefix_scan, chunks, dim3(kPrefixThreads), 0, s, J);
+    int err = check_launch("prefix-sum kernels");
+    if (err) return err;
+    const uint32_t nb = (J.n + kPrefixThreads - 1u) / kPrefixThreads;  // groups of outputs
+    if (method == MGP_MULTINOMIAL) {
+        hipLaunchKernelGGL(k_prefix_multinomial, dim3(nb, R), dim3(kPrefixThreads), 0, s, J);
+    } else {
+        hipLaunchKernelGGL(k_prefix_brackets, dim3(nb / kPrefixThreads + 1u, R), dim3(kPrefixThreads), 0, s, J, nb);
+        hipLaunchKernelGGL(k_prefix_systematic, dim3(nb, R), dim3(kPrefixThreads), 0, s, J);
+    }
+    return check_launch("prefix-sum search kernel");
 }
 
 }  // namespace mgp
@@ -391,7 +408,8 @@ int mgp_prefix_workspace_size(int32_t n, size_t* bytes)
     clear_error();
     if (!bytes) return fail(MGP_EINVAL, "bytes is NULL");
     if (n < 1) return fail(MGP_EINVAL, "n must be >= 1 (got %d)", n);
-    *bytes = prefix_layout((uint32_t)n).total;
+    PrefixJob J{};
+    *bytes = workspace_bytes(1u) + prefix_region((uint32_t)n, &J);
     return MGP_OK;
 }
 
@@ -407,13 +425,13 @@ int mgp_resample_prefix(const float* w_dev, int32_t n, int32_t method, uint64_t 
     if (!workspace_dev) return fail(MGP_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace_dev & 255u) != 0) return fail(MGP_EINVAL, "workspace must be 256-byte aligned");
     const uint32_t un = (uint32_t)n;
-    const PrefixLayout L = prefix_layout(un);
-    if (workspace_bytes_ < L.total)
-        return fail(MGP_ERANGE, "workspace has %zu bytes, needs %zu", workspace_bytes_, L.total);
+    PrefixJob J{};
+    const size_t need = workspace_bytes(1u) + prefix_region(un, &J);
+    if (workspace_bytes_ < need) return fail(MGP_ERANGE, "workspace has %zu bytes, needs %zu", workspace_bytes_, need);
     char* ws = static_cast<char*>(workspace_dev);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // 1. validation, max and fp64 sum: the reduction and finalize step of the
-    //    other resamplers (one explicit iteration, no offsets, no mirror)
+    // validation, max and fp64 sum: the reduction and finalize step of the
+    // other resamplers (one explicit iteration, no offsets, no mirror)
     Params p;
     p.variant = kMetropolis;
     p.B = 1;
@@ -422,43 +440,17 @@ int mgp_resample_prefix(const float* w_dev, int32_t n, int32_t method, uint64_t 
     p.stream_id = stream_id;
     p.partition_bytes = 128;
     p.b_max = 1;
-    int err = enqueue_reduce_finalize(w_dev, un, p, false, ws, stats_dev, s);
+    const int err = enqueue_reduce_finalize(w_dev, un, p, false, ws, stats_dev, s);
     if (err) return err;
-    const mgp_stats* st = reinterpret_cast<const mgp_stats*>(ws + kWsStatsOffset);
-    const uint32_t nch = (un + kChunk - 1u) / kChunk;
-    const int l2 = ceil_log2(un);
-    const uint32_t vec = ((uintptr_t)w_dev & 15u) == 0 ? 1u : 0u;
-    uint64_t* chunk_sum = reinterpret_cast<uint64_t*>(ws + L.chunk_sum);
-    uint64_t* chunk_excl = reinterpret_cast<uint64_t*>(ws + L.chunk_excl);
-    uint64_t* incl = reinterpret_cast<uint64_t*>(ws + L.incl);
-    PrefixHeader* hdr = reinterpret_cast<PrefixHeader*>(ws + L.hdr);
-    Tree tree{};
-    tree.top = L.top;
-    for (int k = 1; k <= L.top; ++k) {
-        tree.t[k] = reinterpret_cast<uint64_t*>(ws + L.level[k]);
-        tree.count[k] = L.count[k];
-    }
-    // 2. the fixed-point prefix sum and the tree
-    hipLaunchKernelGGL(k_prefix_chunks, dim3(nch), dim3(kPrefixThreads), 0, s, w_dev, un, l2, vec, st, chunk_sum);
-    hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kPrefixThreads), 0, s, chunk_sum, nch, l2, st, chunk_excl, hdr);
-    hipLaunchKernelGGL(k_prefix_scan, dim3(nch), dim3(kPrefixThreads), 0, s, w_dev, un, vec, hdr, chunk_excl, incl,
-                       tree);
-    err = check_launch("prefix-sum kernels");
-    if (err) return err;
-    // 3. thresholds and the search
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint32_t nb = (un + kPrefixThreads - 1u) / kPrefixThreads;  // groups of outputs
-    if (method == MGP_MULTINOMIAL) {
-        hipLaunchKernelGGL(k_prefix_multinomial, dim3(nb), dim3(kPrefixThreads), 0, s, un, hdr, tree, incl, k0, k1,
-                           stream_id, ancestors_dev);
-    } else {
-        uint32_t* bracket = reinterpret_cast<uint32_t*>(ws + L.bracket);
-        hipLaunchKernelGGL(k_prefix_brackets, dim3(nb / kPrefixThreads + 1u), dim3(kPrefixThreads), 0, s, un, nb, hdr,
-                           tree, incl, k0, k1, stream_id, bracket);
-        hipLaunchKernelGGL(k_prefix_systematic, dim3(nb), dim3(kPrefixThreads), 0, s, un, hdr, bracket, incl, k0, k1,
-                           stream_id, ancestors_dev);
-    }
-    return check_launch("prefix-sum search kernel");
+    J.w = w_dev;
+    J.stats = reinterpret_cast<const mgp_stats*>(ws + kWsStatsOffset);
+    J.region = ws + workspace_bytes(1u);
+    J.anc = ancestors_dev;
+    J.vec = ((uintptr_t)w_dev & 15u) == 0 ? 1u : 0u;
+    J.key0 = (uint32_t)seed;
+    J.key1 = (uint32_t)(seed >> 32);
+    J.stream0 = stream_id;
+    return enqueue_prefix(J, 1u, method, s);
 }
 
 }  // extern "C"

@@ -45,6 +45,7 @@
 #include "mgp_batch_internal.h"
 #include "mgp_device.h"
 #include "mgp_internal.h"
+#include "mgp_prefix.h"
 #include "mgp_reduce.h"
 
 namespace mgp {
@@ -275,6 +276,8 @@ struct mgp_sir_filter {
     uint32_t key0 = 0, key1 = 0;
     double sigma_v = 0.0;
     LoopShape shape{256, 4, 1};
+    int prefix_method = -1;   // MGP_MULTINOMIAL or MGP_SYSTEMATIC for a prefix-sum stage 2
+    PrefixJob job{};          // its scan regions (one per run) and run strides
     char* dmem = nullptr;
     size_t dmem_bytes = 0;
     float *x = nullptr, *w = nullptr, *xbar = nullptr;
@@ -314,7 +317,9 @@ size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
 int validate(const mgp_sir_config* c)
 {
     if (!c) return fail(MGP_EINVAL, "config is NULL");
-    if (c->variant < MGP_METROPOLIS || c->variant > MGP_MEGOPOLIS) return fail(MGP_EINVAL, "unknown variant %d", c->variant);
+    if (c->variant < MGP_METROPOLIS || c->variant > MGP_SIR_SYSTEMATIC)
+        return fail(MGP_EINVAL, "unknown variant %d", c->variant);
+    const bool prefix = c->variant == MGP_SIR_MULTINOMIAL || c->variant == MGP_SIR_SYSTEMATIC;
     if (c->runs < 1 || c->runs > 65535) return fail(MGP_ERANGE, "runs = %d outside [1, 65535]", c->runs);
     if (c->n < 1 || (uint32_t)c->n > kBatchMaxN) return fail(MGP_ERANGE, "n = %d out of range", c->n);
     if ((uint64_t)c->runs * (uint64_t)c->n > (1ull << 32)) return fail(MGP_ERANGE, "runs * n above 2^32");
@@ -323,11 +328,11 @@ int validate(const mgp_sir_config* c)
     if (pb < 4u || pb % 4u) return fail(MGP_EINVAL, "partition_bytes must be a positive multiple of 4");
     const uint32_t bmax = c->b_max ? c->b_max : kDefaultBMax;
     if (bmax > kBMaxLimit) return fail(MGP_ERANGE, "b_max above %u", kBMaxLimit);
-    if (c->B == 0 && (!(c->epsilon > 0.0) || !(c->epsilon <= 1.0)))
+    if (!prefix && c->B == 0 && (!(c->epsilon > 0.0) || !(c->epsilon <= 1.0)))
         return fail(MGP_EINVAL, "epsilon must be in (0, 1] when B is 0");
-    if (c->B > bmax) return fail(MGP_ERANGE, "B = %u above b_max = %u", c->B, bmax);
+    if (!prefix && c->B > bmax) return fail(MGP_ERANGE, "B = %u above b_max = %u", c->B, bmax);
     if (c->reserved || c->reserved2) return fail(MGP_EINVAL, "reserved must be 0");
-    if (c->block_threads || c->particles_per_thread) {
+    if (!prefix && (c->block_threads || c->particles_per_thread)) {
         const LoopShape want{c->block_threads ? c->block_threads : 256,
                              c->particles_per_thread ? c->particles_per_thread : (c->variant == MGP_MEGOPOLIS ? 4 : 1),
                              1};
@@ -367,8 +372,18 @@ int enqueue_predict(mgp_sir_filter* f, uint32_t t, bool with_mean, hipStream_t s
     return check_launch("SIR predict/update");
 }
 
-int enqueue_resample(mgp_sir_filter* f, hipStream_t s)
+int enqueue_resample(mgp_sir_filter* f, uint32_t t, hipStream_t s)
 {
+    if (f->prefix_method >= 0) {
+        // stage 1 wrote the partials: the finalize step for each run's stats
+        // (validation, max), then the prefix-sum method with the copy
+        // x_bar_i = x_{a_i}, under key seed + t 2^32 and stream r
+        int rc = enqueue_batch_finalize(f->d_fd, f->R, f->d_parts, f->d_stats, f->d_qcount, s);
+        if (rc) return rc;
+        PrefixJob J = f->job;
+        J.key1 = f->key1 + t;
+        return enqueue_prefix(J, f->R, f->prefix_method, s);
+    }
     // stage 1 wrote the partials and the mirror: finalize and accept loop only
     return enqueue_batch(f->cfg.variant, f->shape, f->d_fd, f->R, nullptr, 0u, f->d_parts, f->d_stats, f->d_lt,
                          f->grid, f->d_qoff, f->d_qcount, (uint32_t)f->nxcd, 1u, s);
@@ -401,7 +416,7 @@ int enqueue_steps(mgp_sir_filter* f, hipStream_t s)
     for (uint32_t t = 1; t <= f->T; ++t) {
         int rc = enqueue_predict(f, t, t > 1, s);
         if (!rc && t > 1) rc = enqueue_mean_final(f, t - 1, s);
-        if (!rc) rc = enqueue_resample(f, s);
+        if (!rc) rc = enqueue_resample(f, t, s);
         if (rc) return rc;
     }
     return enqueue_estimate(f, f->T, s);
@@ -463,6 +478,8 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->key1 = (uint32_t)(cfg->seed >> 32);
     f->sigma_v = sqrt(10.0);
     const bool mego = cfg->variant == MGP_MEGOPOLIS;
+    const bool prefix = cfg->variant == MGP_SIR_MULTINOMIAL || cfg->variant == MGP_SIR_SYSTEMATIC;
+    f->prefix_method = prefix ? (cfg->variant == MGP_SIR_MULTINOMIAL ? MGP_MULTINOMIAL : MGP_SYSTEMATIC) : -1;
     f->shape = LoopShape{cfg->block_threads ? cfg->block_threads : 256,
                          cfg->particles_per_thread ? cfg->particles_per_thread : (mego ? 4 : 1), 1};
     if (hipGetDevice(&f->device) != hipSuccess) return bail(fail(MGP_EHIP, "hipGetDevice failed"));
@@ -472,7 +489,7 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->nxcd = (prop.multiProcessorCount >= 64 && prop.multiProcessorCount % kMaxXcd == 0) ? kMaxXcd : 1;
 
     // ---- accept-loop tiles: R equal filters, XCD-balanced
-    const uint32_t B_fixed = cfg->B;
+    const uint32_t B_fixed = prefix ? 1u : cfg->B;  // prefix-sum stage 2: the finalize step only validates
     std::vector<uint32_t> ns(f->R, f->n);
     std::vector<double> cost(f->R, (double)f->n * std::max<uint32_t>(1u, B_fixed ? B_fixed : 32u));
     std::vector<LTile> table;
@@ -511,6 +528,8 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     const size_t offs_row = align256(sizeof(uint32_t) * (size_t)offs_cap);
     const size_t o_offs = mego ? take((size_t)f->R * offs_row) : 0;
     const size_t o_mirror = mego ? take((size_t)f->R * mirror_row) : 0;
+    const size_t prefix_row = prefix ? align256(prefix_region(f->n, &f->job)) : 0;
+    const size_t o_prefix = prefix ? take((size_t)f->R * prefix_row) : 0;
     f->dmem_bytes = off;
     if (hipMalloc(&f->dmem, f->dmem_bytes) != hipSuccess)
         return bail(fail(MGP_ENOMEM, "could not allocate %zu bytes for the filter", f->dmem_bytes));
@@ -530,6 +549,25 @@ int mgp_sir_create(const mgp_sir_config* cfg, void* stream, mgp_sir_filter** out
     f->d_qoff = f->d_qcount + (kMaxXcd + 1);
     f->d_lt = reinterpret_cast<LTile*>(f->dmem + o_lt);
 
+    if (prefix) {
+        PrefixJob& J = f->job;
+        J.w = f->w;
+        J.w_ld = f->ld;
+        J.stats = f->d_stats;
+        J.region = f->dmem + o_prefix;
+        J.region_ld = prefix_row;
+        J.anc = f->anc;
+        J.anc_ld = f->ld;
+        J.states = f->x;
+        J.out = f->xbar;
+        J.rows_ld = f->ld;
+        J.d = 1;
+        J.vec4 = 0;
+        J.vec = 1;  // rows are 256-byte aligned
+        J.key0 = f->key0;
+        J.key1 = f->key1;
+        J.stream0 = 0;
+    }
     std::vector<FilterDev> fd(f->R);
     const uint32_t n_w = f->cfg.partition_bytes / 4u;
     for (uint32_t r = 0; r < f->R; ++r) {
@@ -615,7 +653,7 @@ int mgp_sir_resample(mgp_sir_filter* f, int32_t t, void* stream)
     clear_error();
     if (!f) return fail(MGP_EINVAL, "filter is NULL");
     int rc = check_stage(f, t, 2);
-    if (!rc) rc = enqueue_resample(f, static_cast<hipStream_t>(stream));
+    if (!rc) rc = enqueue_resample(f, (uint32_t)t, static_cast<hipStream_t>(stream));
     if (!rc) advance(f);
     return rc;
 }

@@ -20,8 +20,10 @@ MGP_OK, MGP_EINVAL, MGP_ERANGE, MGP_ENOMEM, MGP_EHIP, MGP_EBUSY, MGP_EWEIGHTS = 
 MGP_METROPOLIS, MGP_C1, MGP_C2, MGP_MEGOPOLIS = 0, 1, 2, 3
 MGP_MULTINOMIAL, MGP_SYSTEMATIC = 0, 1
 PREFIX_METHODS = {"multinomial": MGP_MULTINOMIAL, "systematic": MGP_SYSTEMATIC}
+MGP_SIR_MULTINOMIAL, MGP_SIR_SYSTEMATIC = 4, 5
 MGP_NOALLOC_SCRATCH_BYTES = 64 << 20
 VARIANTS = {"metropolis": MGP_METROPOLIS, "c1": MGP_C1, "c2": MGP_C2, "megopolis": MGP_MEGOPOLIS}
+SIR_VARIANTS = {**VARIANTS, "multinomial": MGP_SIR_MULTINOMIAL, "systematic": MGP_SIR_SYSTEMATIC}
 
 
 class MgpError(RuntimeError):
@@ -775,12 +777,13 @@ class Server:
 class SirFilter:
     """Owns an mgp_sir_filter: R runs of the SIR filter of Algorithm 6, n
     particles each, T steps, stage 2 done by `variant` with B iterations (or B
-    from epsilon per step when B is 0)."""
+    from epsilon per step when B is 0), or by the prefix-sum method
+    "multinomial" or "systematic" (Algorithms 7 and 8; B unused)."""
 
     def __init__(self, runs: int, n: int, steps: int, variant="megopolis", B: int = 16, epsilon: float = 0.1,
                  seed: int = 0, partition_bytes: int = 128, b_max: int = 0, use_graph: bool = True,
                  block_threads: int = 0, particles_per_thread: int = 0, stream: int | None = None):
-        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        v = SIR_VARIANTS[variant] if isinstance(variant, str) else int(variant)
         cfg = mgp_sir_config(v, int(runs), int(n), int(steps), int(B), int(partition_bytes), float(epsilon),
                              int(seed) & (2**64 - 1), int(b_max), 1 if use_graph else 0, int(block_threads),
                              int(particles_per_thread), 0, 0)

@@ -1,8 +1,10 @@
 """The SIR filter of Section 7 (Algorithm 6) on the GPU against the oracle:
 every stage of every step element by element (predicted particles, weights,
 ancestors, resampled particles, estimate), whole runs of every variant with
-fixed B and with B from epsilon, the degenerate step, the graph against the
-stage-by-stage launches, and launch shapes. Inputs come from the seeded
+fixed B and with B from epsilon, and of the prefix-sum methods of Table 2's
+unbiased rows (multinomial and systematic, Algorithms 7 and 8), the
+degenerate step, the graph against the stage-by-stage launches, and launch
+shapes. Inputs come from the seeded
 generators only; the oracle computes its own chain from them.
 
 Stage 1 evaluates log, cos and exp in fp64 on both sides (device math
@@ -52,7 +54,16 @@ def make(env, R, n, T, z, x0, **kw):
     return f
 
 
-@pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2"])
+PREFIX = ("multinomial", "systematic")
+
+
+def oracle_ancestors(w, variant, B, t, r):
+    if variant in PREFIX:
+        return oracle.resample_prefix(w, variant, oracle.sir_step_seed(SEED, t), stream_id=r)
+    return oracle.resample(w, variant, B, oracle.sir_step_seed(SEED, t), stream_id=r)
+
+
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2", "multinomial", "systematic"])
 def test_every_stage_matches_oracle(env, variant):
     torch, mgp = env
     R, n, T, B = 3, 5003, 4, 12
@@ -70,17 +81,17 @@ def test_every_stage_matches_oracle(env, variant):
             x, w = oracle.sir_predict_update(xbar[r], t, float(z[r, t]), SEED, r)
             np.testing.assert_array_equal(gx[r], x, err_msg=f"x, step {t} run {r}")
             np.testing.assert_array_equal(gw[r], w, err_msg=f"w, step {t} run {r}")
-            anc = oracle.resample(w, variant, B, oracle.sir_step_seed(SEED, t), stream_id=r)
+            anc = oracle_ancestors(w, variant, B, t, r)
             np.testing.assert_array_equal(ga[r], anc, err_msg=f"ancestors, step {t} run {r}")
             xbar[r] = oracle.gather(x, anc).reshape(-1)
             np.testing.assert_array_equal(gxb[r], xbar[r])
             assert abs(est[r, t - 1] - oracle.mean(xbar[r])) <= mean_tol(xbar[r])
-            assert bs[r, t - 1] == B and st[r, t - 1] == 0
+            assert bs[r, t - 1] == (1 if variant in PREFIX else B) and st[r, t - 1] == 0
     f.close()
 
 
 @pytest.mark.parametrize("variant,B", [("megopolis", 16), ("metropolis", 16), ("c1", 16), ("c2", 16),
-                                       ("megopolis", 0), ("c2", 0)])
+                                       ("megopolis", 0), ("c2", 0), ("multinomial", 0), ("systematic", 0)])
 def test_whole_runs_match_oracle(env, variant, B):
     """T = 30 steps of 4 runs, n ragged; B fixed, or (B = 0) from eq. (bcalc)
     with epsilon = 0.1 at every step as in Section 7."""
@@ -143,7 +154,7 @@ def test_small_and_ragged_sizes(env, R, n):
     torch, mgp = env
     T = 6
     _, z, x0 = problem(R, n, T)
-    for variant in ("megopolis", "c2"):
+    for variant in ("megopolis", "c2", "systematic"):
         f = make(env, R, n, T, z, x0, variant=variant, B=7)
         f.run()
         est, bs, st = f.results()
@@ -176,19 +187,20 @@ def test_benchmark_path_100_steps(env):
         np.testing.assert_allclose(est[r], oe, rtol=0, atol=4 * n * 2.0 ** -53 * 40.0)
 
 
-def test_degenerate_step_keeps_predicted_particles(env):
+@pytest.mark.parametrize("variant", ["megopolis", "multinomial"])
+def test_degenerate_step_keeps_predicted_particles(env, variant):
     torch, mgp = env
     R, n, T = 3, 2048, 6
     _, z, x0 = problem(R, n, T)
     z = z.copy()
     z[1, 3] = 1e6  # run 1, step 3: every weight underflows
-    f = make(env, R, n, T, z, x0, variant="megopolis", B=10)
+    f = make(env, R, n, T, z, x0, variant=variant, B=10)
     f.run()
     est, bs, st = f.results()
     assert st[1].tolist() == [0, 0, mgp.MGP_EWEIGHTS, 0, 0, 0] and bs[1, 2] == 0
     assert (st[[0, 2]] == 0).all()
     for r in range(R):
-        oe, ob, ost, oxb = oracle.sir_filter(x0[r], z[r], "megopolis", 10, SEED, r)
+        oe, ob, ost, oxb = oracle.sir_filter(x0[r], z[r], variant, 10, SEED, r)
         np.testing.assert_array_equal(st[r], ost)
         np.testing.assert_array_equal(f.copy("xbar").cpu().numpy()[r], oxb)
         np.testing.assert_allclose(est[r], oe, rtol=0, atol=4 * n * 2.0 ** -53 * 40.0)

@@ -42,7 +42,7 @@ def rmse_of():
             f.run()
             est, bs, st = f.results()
             f.close()
-            assert (st == 0).all() and (bs == B).all()
+            assert (st == 0).all() and (bs == (B if B else 1)).all()
             e = est.reshape(TRAJ, MC, T) - truth[:, None, 1:]
             cache[(variant, B)] = float(np.sqrt(np.mean(e * e, axis=1)).mean(axis=1).mean())
         return cache[(variant, B)]
@@ -77,6 +77,29 @@ def test_table2_rmse_falls_with_B(rmse_of, variant):
     0.017-0.075 per doubling; the runs here share their seeds across B."""
     r16, r32, r64 = (rmse_of(variant, b) for b in (16, 32, 64))
     assert r16 > r32 - 0.005 and r32 > r64 - 0.01 and r16 > r64, (variant, r16, r32, r64)
+
+
+UNBIASED = {r["method"]: r["rmse"] for r in GOLDEN["unbiased"]}
+
+
+@pytest.mark.parametrize("method", ["multinomial", "systematic"])
+def test_unbiased_rows_near_table2(rmse_of, method):
+    """Table 2's unbiased rows: stage 2 by multinomial (Algorithm 7) or
+    systematic (Algorithm 8) resampling through the prefix sum."""
+    got = rmse_of(method, 0)
+    assert abs(got - UNBIASED[method]) < 0.3, (method, got, UNBIASED[method])
+
+
+def test_unbiased_rows_orderings(rmse_of):
+    """Table 2: the unbiased methods have the lowest RMSE (2.944), below C1 at
+    every B (3.10-3.17) and below the B = 16 rows (3.04-3.17), and Megopolis
+    approaches them as B grows (2.948 at B = 64)."""
+    for m in ("multinomial", "systematic"):
+        u = rmse_of(m, 0)
+        for B in (16, 32, 64):
+            assert u < rmse_of("c1", B) - 0.05, (m, B)
+        assert u < rmse_of("megopolis", 16) - 0.02, m
+        assert abs(u - rmse_of("megopolis", 64)) < 0.05, m
 
 
 def test_b_study_claims(rmse_of):
