@@ -22,7 +22,8 @@
 //   k_prefix_top      one block: exclusive sums over the chunks, the header
 //   k_prefix_scan     per chunk: the inclusive sums (coalesced through LDS)
 //                     and the tree's entries that fall in the chunk
-//   multinomial:      k_prefix_multinomial, a descent per output
+//   multinomial:      k_prefix_multinomial, a descent per output (eight
+//                     lanes share each row read)
 //   systematic:       k_prefix_brackets, a descent for every 256th output,
 //                     then k_prefix_systematic, a bisection per output between
 //                     the two brackets of its group (thresholds rise with i)
@@ -143,26 +144,50 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix_chunks(PrefixJob J)
 }
 
 // One block per run: chunk_excl[c] = sum of chunk_sum[0..c), and the header.
+// The chunk sums go through LDS a tile of kChunk at a time, so that the
+// loads and stores are coalesced; each thread scans kPrefixPer consecutive
+// sums of the tile, and the tile's total carries into the next.
 __global__ __launch_bounds__(kPrefixThreads) void k_prefix_top(PrefixJob J)
 {
+    __shared__ uint64_t tile[kChunk];
     const uint64_t* chunk_sum = at<uint64_t>(J, J.o_sum);
     uint64_t* chunk_excl = at<uint64_t>(J, J.o_excl);
-    // thread t owns chunks [t * per, (t + 1) * per)
-    const uint32_t per = (J.nch + kPrefixThreads - 1u) / kPrefixThreads;
-    const uint32_t c0 = threadIdx.x * per;
-    uint64_t s = 0;
-    for (uint32_t c = c0; c < c0 + per && c < J.nch; ++c) s += chunk_sum[c];
-    uint64_t total = 0;
-    uint64_t run = block_exclusive_scan(s, &total);
-    for (uint32_t c = c0; c < c0 + per && c < J.nch; ++c) {
-        chunk_excl[c] = run;
-        run += chunk_sum[c];
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < J.nch; base += kChunk) {
+#pragma unroll
+        for (uint32_t e = 0; e < kPrefixPer; ++e) {
+            const uint32_t c = base + e * kPrefixThreads + threadIdx.x;
+            tile[e * kPrefixThreads + threadIdx.x] = c < J.nch ? chunk_sum[c] : 0u;
+        }
+        __syncthreads();
+        uint64_t v[kPrefixPer];
+        uint64_t s = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < kPrefixPer; ++e) {
+            v[e] = tile[threadIdx.x * kPrefixPer + e];
+            s += v[e];
+        }
+        uint64_t total = 0;
+        uint64_t run = carry + block_exclusive_scan(s, &total);
+#pragma unroll
+        for (uint32_t e = 0; e < kPrefixPer; ++e) {
+            tile[threadIdx.x * kPrefixPer + e] = run;
+            run += v[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t e = 0; e < kPrefixPer; ++e) {
+            const uint32_t c = base + e * kPrefixThreads + threadIdx.x;
+            if (c < J.nch) chunk_excl[c] = tile[e * kPrefixThreads + threadIdx.x];
+        }
+        carry += total;
+        __syncthreads();  // the tile is overwritten next
     }
     if (threadIdx.x == 0) {
         const mgp_stats& st = J.stats[blockIdx.y];
         const bool ok = st.status == MGP_OK;
         PrefixHeader h;
-        h.total = ok ? total : 0u;
+        h.total = ok ? carry : 0u;
         h.K = ok ? fixed_exponent(st.w_max, J.log2n) : 0;
         h.valid = ok ? 1 : 0;
         *at<PrefixHeader>(J, J.o_hdr) = h;
@@ -287,16 +312,68 @@ __device__ __forceinline__ void emit(const PrefixJob& J, uint32_t i, int32_t a)
     }
 }
 
+// Multinomial: the descents of a wave's 64 outputs, eight lanes to a row.
+// A lane that read a whole 128-byte row by itself would make each load
+// instruction of the wave touch 64 lines, and the address path, not the
+// memory, would bound the kernel. Here the lanes of an octet (8 lanes) read
+// the 16-byte quarters of one row together, so an instruction touches 8
+// lines: lane l serves outputs r*8 + l/8 (r = 0..7) of the wave, reading
+// their rows' quarter l mod 8, and the octet adds up its counts. Lane l draws
+// the threshold of output l, and gets back the ancestor of output l, by
+// cross-lane permutes. Every lane of the wave runs to the end (outputs past n
+// search too, and are not stored).
 __global__ __launch_bounds__(kPrefixThreads) void k_prefix_multinomial(PrefixJob J)
 {
+    constexpr uint32_t kOct = 8;  // lanes per row; also the outputs per lane
+    const uint32_t lane = threadIdx.x & 63u;
     const uint32_t i = blockIdx.x * kPrefixThreads + threadIdx.x;
-    if (i >= J.n) return;
     const PrefixHeader h = *at<PrefixHeader>(J, J.o_hdr);
     if (!h.valid) {
-        emit(J, i, -1);
+        if (i < J.n) emit(J, i, -1);
         return;
     }
-    emit(J, i, (int32_t)descend(J, prefix_threshold<MGP_MULTINOMIAL>(J, h.total, i)));
+    const uint64_t t_mine = prefix_threshold<MGP_MULTINOMIAL>(J, h.total, i < J.n ? i : J.n - 1u);
+    const uint32_t oct = lane / kOct, quarter = lane % kOct;
+    uint64_t t[kOct];
+    uint32_t g[kOct];
+#pragma unroll
+    for (uint32_t r = 0; r < kOct; ++r) {
+        const int src = (int)(r * kOct + oct);
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)t_mine, src, 64);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(t_mine >> 32), src, 64);
+        t[r] = (uint64_t)lo | ((uint64_t)hi << 32);
+        g[r] = 0u;
+    }
+    for (int k = J.top; k >= 0; --k) {
+        const uint64_t* lv = at<uint64_t>(J, k ? J.o_level[k] : J.o_incl) + quarter * 2u;
+        ulonglong2 v[kOct];
+#pragma unroll
+        for (uint32_t r = 0; r < kOct; ++r) v[r] = *reinterpret_cast<const ulonglong2*>(lv + (uint64_t)g[r] * kFan);
+        // counts of up to 16 per row, one byte each: outputs 0-3 in c0, 4-7 in c1
+        uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kOct; ++r) {
+            const uint32_t c = (v[r].x <= t[r] ? 1u : 0u) + (v[r].y <= t[r] ? 1u : 0u);
+            if (r < 4) c0 |= c << (8u * r);
+            else c1 |= c << (8u * (r - 4u));
+        }
+#pragma unroll
+        for (int off = 1; off < (int)kOct; off <<= 1) {
+            c0 += (uint32_t)__shfl_xor((int)c0, off, 64);
+            c1 += (uint32_t)__shfl_xor((int)c1, off, 64);
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < kOct; ++r)
+            g[r] = g[r] * kFan + (((r < 4 ? c0 : c1) >> (8u * (r % 4u))) & 0xFFu);
+    }
+    // output l's ancestor is g[l / 8] of the octet l mod 8
+    uint32_t a = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kOct; ++r) {
+        const uint32_t x = (uint32_t)__shfl((int)g[r], (int)((lane % kOct) * kOct), 64);
+        if (lane / kOct == r) a = x;
+    }
+    if (i < J.n) emit(J, i, (int32_t)a);
 }
 
 // Systematic, first pass: the ancestors of outputs 0, G, 2G, ... (G =
