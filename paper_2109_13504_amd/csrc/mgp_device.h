@@ -179,137 +179,115 @@ struct Unroll {
     static constexpr uint32_t value = (V == kMegopolis) ? 5u : 20u;
 };
 
+// What a chain carries from block to block, and what is fixed for it.
+struct ChainState {
+    uint32_t k;  // current ancestor
+    float wk;    // its weight
+};
+
+struct ChainFixed {
+    uint32_t i;          // particle (random draws, C1/C2 group)
+    uint32_t group;      // i / 32
+    uint32_t i_aligned;  // Megopolis: segment base of the start position
+    uint32_t i_low;      // Megopolis: place of the start position in its segment
+    uint32_t c1_part;    // C1: the group's partition
+};
+
+// Steps q U .. q U + cnt - 1 of a chain (cnt = U for a whole block; the last
+// block of B mod U steps passes Partial and its count). The candidates and
+// their weights come first: they do not depend on the chain, so all of the
+// block's loads are in flight together; then the serial accept steps.
+// Partial skips the steps past cnt (cnt is wave-uniform), including their
+// generator calls and loads.
+template <int V, bool Narrow, bool Shared, bool Partial>
+__device__ __forceinline__ void chain_block(const LoopParams& P, const ChainFixed& F, uint32_t q, uint32_t cnt,
+                                            ChainState& c)
+{
+    constexpr uint32_t U = Unroll<V>::value;
+    constexpr bool kShare = Shared && V == kC2;
+    const float* __restrict__ w = P.w;
+    UBlock ub;
+    Words jb{}, pb{}, pmine{};
+    uint32_t jj[U];
+    float wj[U];
+    if constexpr (kShare) {
+        // lane k (< U / 4) of the half-wave: the call of block q U / 4 + k
+        const uint32_t k = __lane_id() & 31u;
+        pmine = philox(q * (U / 4) + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, F.group, P.key0, P.key1);
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < U; ++s) {
+        if (Partial && s >= cnt) continue;
+        const uint32_t b = q * U + s;
+        uint32_t j;
+        if constexpr (V == kMegopolis) {
+            j = megopolis_index(F.i_aligned, F.i_low, offset_at(P, b), P.n, P.seg_mask);
+        } else {
+            if (s % 4 == 0) {
+                const uint32_t blk = q * (U / 4) + s / 4;
+                jb = philox(blk, kTagJ, P.stream_id, F.i, P.key0, P.key1);
+                if constexpr (V == kC2 && !kShare) pb = philox(blk, kTagC2Part, P.stream_id, F.group, P.key0, P.key1);
+            }
+            const uint32_t jw = word(jb, s % 4);
+            if constexpr (V == kMetropolis) {
+                j = uniform_index(jw, P.n);
+            } else if constexpr (V == kC1) {
+                j = partition_index(F.c1_part, jw, P.n, P.n_w);
+            } else {
+                uint32_t pw;
+                if constexpr (kShare)
+                    pw = (uint32_t)__shfl((int)word(pmine, s % 4), (int)((__lane_id() & 32u) + s / 4), 64);
+                else
+                    pw = word(pb, s % 4);
+                j = partition_index(uniform_index(pw, P.n_part), jw, P.n, P.n_w);
+            }
+        }
+        jj[s] = j;
+        wj[s] = load_weight<Narrow>(w, j);
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < U; ++s) {
+        if (Partial && s >= cnt) continue;
+        if (s % 5 == 0) ub = u_block(philox(q * (U / 5) + s / 5, kTagU, P.stream_id, F.i, P.key0, P.key1));
+        const float p = ub.u[s % 5] * c.wk;
+        const bool acc = p <= wj[s];
+        c.k = acc ? jj[s] : c.k;
+        c.wk = acc ? wj[s] : c.wk;
+    }
+}
+
 // The B-step chain of particle i; returns its ancestor. The chain starts at
 // input position pos (i itself when inputs and outputs are the same
 // particles, i mod n for M != N resampling): the Megopolis segment
-// arithmetic uses pos, the random draws and the C1/C2 group use i.
+// arithmetic uses pos, the random draws and the C1/C2 group use i. The steps
+// run in blocks of U (Unroll), the last B mod U of them as one partial block.
 // Shared (C2 only): every lane of the wave runs a chain, and the 32 lanes of
 // each half-wave hold the 32 particles of one group (i - lane a multiple of
 // 32 within the half-wave). The group's partition draw of each step is the
 // same for its 32 particles, so instead of each lane calling the generator
 // once per four steps, lane k of the half-wave makes the call of the k-th
-// four-step block of the next twenty steps and the others read its words
-// with a cross-lane permute: one call per lane per twenty steps (and one for
-// the B mod 20 steps of the tail).
+// four-step block of the block's twenty steps and the others read its words
+// with a cross-lane permute: one call per lane per twenty steps.
 template <int V, bool Narrow, bool Shared = false>
 __device__ __forceinline__ uint32_t run_chain(const LoopParams& P, uint32_t i, uint32_t pos)
 {
-    const float* __restrict__ w = P.w;
-    uint32_t k = pos;
-    float wk = load_weight<Narrow>(w, pos);
-    const uint32_t i_aligned = pos & ~P.seg_mask;
-    const uint32_t i_low = pos & P.seg_mask;
-    const uint32_t group = i / kSegment;
-
-    uint32_t c1_part = 0;
+    ChainFixed F;
+    F.i = i;
+    F.group = i / kSegment;
+    F.i_aligned = pos & ~P.seg_mask;
+    F.i_low = pos & P.seg_mask;
+    F.c1_part = 0;
     if constexpr (V == kC1) {
-        const Words px = philox(0u, kTagC1Part, P.stream_id, group, P.key0, P.key1);
-        c1_part = uniform_index(px.x0, P.n_part);
+        const Words px = philox(0u, kTagC1Part, P.stream_id, F.group, P.key0, P.key1);
+        F.c1_part = uniform_index(px.x0, P.n_part);
     }
-
+    ChainState c{pos, load_weight<Narrow>(P.w, pos)};
     constexpr uint32_t U = Unroll<V>::value;
-    constexpr bool kShare = Shared && V == kC2;
     const uint32_t nblk = P.B / U;
-    for (uint32_t q = 0; q < nblk; ++q) {
-        UBlock ub;
-        Words jb{}, pb{}, pmine{};
-        uint32_t jj[U];
-        float wj[U];
-        if constexpr (kShare) {
-            // lane k (< U / 4) of the half-wave: the call of block q U / 4 + k
-            const uint32_t k = __lane_id() & 31u;
-            pmine = philox(q * (U / 4) + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, group, P.key0, P.key1);
-        }
-        // candidates and their weights first: they do not depend on k
-#pragma unroll
-        for (uint32_t s = 0; s < U; ++s) {
-            const uint32_t b = q * U + s;
-            uint32_t j;
-            if constexpr (V == kMegopolis) {
-                j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n, P.seg_mask);
-            } else {
-                if (s % 4 == 0) {
-                    const uint32_t blk = q * (U / 4) + s / 4;
-                    jb = philox(blk, kTagJ, P.stream_id, i, P.key0, P.key1);
-                    if constexpr (V == kC2 && !kShare) pb = philox(blk, kTagC2Part, P.stream_id, group, P.key0, P.key1);
-                }
-                const uint32_t jw = word(jb, s % 4);
-                if constexpr (V == kMetropolis) {
-                    j = uniform_index(jw, P.n);
-                } else if constexpr (V == kC1) {
-                    j = partition_index(c1_part, jw, P.n, P.n_w);
-                } else {
-                    uint32_t pw;
-                    if constexpr (kShare)
-                        pw = (uint32_t)__shfl((int)word(pmine, s % 4), (int)((__lane_id() & 32u) + s / 4), 64);
-                    else
-                        pw = word(pb, s % 4);
-                    j = partition_index(uniform_index(pw, P.n_part), jw, P.n, P.n_w);
-                }
-            }
-            jj[s] = j;
-            wj[s] = load_weight<Narrow>(w, j);
-        }
-        // then the serial accept chain
-#pragma unroll
-        for (uint32_t s = 0; s < U; ++s) {
-            if (s % 5 == 0) ub = u_block(philox(q * (U / 5) + s / 5, kTagU, P.stream_id, i, P.key0, P.key1));
-            const float p = ub.u[s % 5] * wk;
-            const bool acc = p <= wj[s];
-            k = acc ? jj[s] : k;
-            wk = acc ? wj[s] : wk;
-        }
-    }
-
-    // remaining B mod U steps, one at a time; a generator block is refreshed
-    // when a step starts a new one (the first tail step is a multiple of 20,
-    // or of 5 for Megopolis, which draws no j)
-    UBlock ub{};
-    Words jb{}, pb{};
-    const uint32_t b0 = nblk * U;
-    if constexpr (kShare) {
-        // the tail needs at most U / 4 partition blocks, from block b0 / 4 on:
-        // lane k (< U / 4) of the half-wave makes the call of block b0 / 4 + k
-        if (b0 < P.B) {
-            const uint32_t k = __lane_id() & 31u;
-            pb = philox(b0 / 4u + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, group, P.key0, P.key1);
-        }
-    }
-    for (uint32_t b = b0; b < P.B; ++b) {
-        const uint32_t r5 = b % 5u;
-        const uint32_t r4 = b % 4u;
-        if (r5 == 0u) ub = u_block(philox(b / 5u, kTagU, P.stream_id, i, P.key0, P.key1));
-        uint32_t j;
-        if constexpr (V == kMegopolis) {
-            j = megopolis_index(i_aligned, i_low, offset_at(P, b), P.n, P.seg_mask);
-        } else {
-            if (r4 == 0u) {
-                jb = philox(b / 4u, kTagJ, P.stream_id, i, P.key0, P.key1);
-                if constexpr (V == kC2 && !kShare) pb = philox(b / 4u, kTagC2Part, P.stream_id, group, P.key0, P.key1);
-            }
-            const uint32_t jw = word(jb, r4);
-            if constexpr (V == kMetropolis) {
-                j = uniform_index(jw, P.n);
-            } else if constexpr (V == kC1) {
-                j = partition_index(c1_part, jw, P.n, P.n_w);
-            } else {
-                uint32_t pw;
-                if constexpr (kShare)
-                    pw = (uint32_t)__shfl((int)word(pb, r4), (int)((__lane_id() & 32u) + (b - b0) / 4u), 64);
-                else
-                    pw = word(pb, r4);
-                j = partition_index(uniform_index(pw, P.n_part), jw, P.n, P.n_w);
-            }
-        }
-        const float wjv = load_weight<Narrow>(w, j);
-        const float u = r5 == 0 ? ub.u[0] : r5 == 1 ? ub.u[1] : r5 == 2 ? ub.u[2] : r5 == 3 ? ub.u[3] : ub.u[4];
-        const float p = u * wk;
-        if (p <= wjv) {
-            k = j;
-            wk = wjv;
-        }
-    }
-    return k;
+    for (uint32_t q = 0; q < nblk; ++q) chain_block<V, Narrow, Shared, false>(P, F, q, U, c);
+    const uint32_t rest = P.B - nblk * U;
+    if (rest) chain_block<V, Narrow, Shared, true>(P, F, nblk, rest, c);
+    return c.k;
 }
 
 template <int V, bool Narrow, bool Shared = false>
