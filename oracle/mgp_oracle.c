@@ -52,6 +52,14 @@
  *
  * Each function computes what its definition states, one particle and one
  * step at a time, with no blocking, fusion or reordering.
+ *
+ * Parity unpinned: the paper does not fix the stream layout above, the two
+ * word-to-number maps, the clamps of B (at least 1, at most b_max, 1 when the
+ * mean weight reaches the largest), the C1/C2 partition of a ragged last
+ * group, the SIR noise layout and prior, the M != N start positions, or the
+ * fixed-point form of the prefix sums. These are this library's readings,
+ * checked here by self-consistency and by the statistical tests (uniformity,
+ * moments, the paper's bias and MSE figures), not by values the paper prints.
  */
 #include <math.h>
 #include <stddef.h>
