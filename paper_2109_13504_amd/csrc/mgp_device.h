@@ -193,6 +193,17 @@ struct ChainFixed {
     uint32_t c1_part;    // C1: the group's partition
 };
 
+// The particle index as an opaque value: an empty volatile asm statement
+// that the compiler may not move out of the branch it sits in, so that a
+// generator call taking its result stays behind that branch's test instead
+// of being computed ahead of it for steps that do not run. No instruction
+// is emitted.
+__device__ __forceinline__ uint32_t pinned(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Steps q U .. q U + cnt - 1 of a chain (cnt = U for a whole block; the last
 // block of B mod U steps passes Partial and its count). The candidates and
 // their weights come first: they do not depend on the chain, so all of the
@@ -204,19 +215,20 @@ __device__ __forceinline__ void chain_block(const LoopParams& P, const ChainFixe
                                             ChainState& c)
 {
     constexpr uint32_t U = Unroll<V>::value;
+    constexpr uint32_t S = U;
     constexpr bool kShare = Shared && V == kC2;
     const float* __restrict__ w = P.w;
     UBlock ub;
     Words jb{}, pb{}, pmine{};
-    uint32_t jj[U];
-    float wj[U];
+    uint32_t jj[S];
+    float wj[S];
     if constexpr (kShare) {
         // lane k (< U / 4) of the half-wave: the call of block q U / 4 + k
         const uint32_t k = __lane_id() & 31u;
         pmine = philox(q * (U / 4) + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, F.group, P.key0, P.key1);
     }
 #pragma unroll
-    for (uint32_t s = 0; s < U; ++s) {
+    for (uint32_t s = 0; s < S; ++s) {
         if (Partial && s >= cnt) continue;
         const uint32_t b = q * U + s;
         uint32_t j;
@@ -225,8 +237,12 @@ __device__ __forceinline__ void chain_block(const LoopParams& P, const ChainFixe
         } else {
             if (s % 4 == 0) {
                 const uint32_t blk = q * (U / 4) + s / 4;
-                jb = philox(blk, kTagJ, P.stream_id, F.i, P.key0, P.key1);
-                if constexpr (V == kC2 && !kShare) pb = philox(blk, kTagC2Part, P.stream_id, F.group, P.key0, P.key1);
+                const uint32_t pi = Partial ? pinned(F.i) : F.i;
+                jb = philox(blk, kTagJ, P.stream_id, pi, P.key0, P.key1);
+                if constexpr (V == kC2 && !kShare) {
+                    const uint32_t pg = Partial ? pinned(F.group) : F.group;
+                    pb = philox(blk, kTagC2Part, P.stream_id, pg, P.key0, P.key1);
+                }
             }
             const uint32_t jw = word(jb, s % 4);
             if constexpr (V == kMetropolis) {
@@ -246,9 +262,12 @@ __device__ __forceinline__ void chain_block(const LoopParams& P, const ChainFixe
         wj[s] = load_weight<Narrow>(w, j);
     }
 #pragma unroll
-    for (uint32_t s = 0; s < U; ++s) {
+    for (uint32_t s = 0; s < S; ++s) {
         if (Partial && s >= cnt) continue;
-        if (s % 5 == 0) ub = u_block(philox(q * (U / 5) + s / 5, kTagU, P.stream_id, F.i, P.key0, P.key1));
+        if (s % 5 == 0) {
+            const uint32_t pi = Partial ? pinned(F.i) : F.i;
+            ub = u_block(philox(q * (U / 5) + s / 5, kTagU, P.stream_id, pi, P.key0, P.key1));
+        }
         const float p = ub.u[s % 5] * c.wk;
         const bool acc = p <= wj[s];
         c.k = acc ? jj[s] : c.k;
