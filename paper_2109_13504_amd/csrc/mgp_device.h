@@ -215,20 +215,19 @@ __device__ __forceinline__ void chain_block(const LoopParams& P, const ChainFixe
                                             ChainState& c)
 {
     constexpr uint32_t U = Unroll<V>::value;
-    constexpr uint32_t S = U;
     constexpr bool kShare = Shared && V == kC2;
     const float* __restrict__ w = P.w;
     UBlock ub;
     Words jb{}, pb{}, pmine{};
-    uint32_t jj[S];
-    float wj[S];
+    uint32_t jj[U];
+    float wj[U];
     if constexpr (kShare) {
         // lane k (< U / 4) of the half-wave: the call of block q U / 4 + k
         const uint32_t k = __lane_id() & 31u;
         pmine = philox(q * (U / 4) + (k < U / 4 ? k : 0u), kTagC2Part, P.stream_id, F.group, P.key0, P.key1);
     }
 #pragma unroll
-    for (uint32_t s = 0; s < S; ++s) {
+    for (uint32_t s = 0; s < U; ++s) {
         if (Partial && s >= cnt) continue;
         const uint32_t b = q * U + s;
         uint32_t j;
@@ -262,7 +261,7 @@ __device__ __forceinline__ void chain_block(const LoopParams& P, const ChainFixe
         wj[s] = load_weight<Narrow>(w, j);
     }
 #pragma unroll
-    for (uint32_t s = 0; s < S; ++s) {
+    for (uint32_t s = 0; s < U; ++s) {
         if (Partial && s >= cnt) continue;
         if (s % 5 == 0) {
             const uint32_t pi = Partial ? pinned(F.i) : F.i;
