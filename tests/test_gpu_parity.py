@@ -73,7 +73,11 @@ def test_ragged_sizes_and_tails(torch_dev, mgp, variant, n):
     w = inputs.gaussian_weights(n, 1.0, 3)
     wd = _to_dev(torch, dev, w)
     r = mgp.Resampler(n)
-    for B in (1, 3, 5, 7, 19, 20, 23, 41):
+    # B mod 20 covers the partial last block of every size class of the
+    # generic chain: inside the first four-step generator group (1, 3), at
+    # its edges (4, 8, 12, 16, 24, 36), across the five-step u groups (5, 7),
+    # a whole block (20) and the longest remainder (19)
+    for B in (1, 3, 4, 5, 7, 8, 12, 16, 19, 20, 23, 24, 36, 41):
         anc = r.resample(wd, variant, B=B, seed=B * 11, stream_id=5).cpu().numpy()
         ref = oracle.resample(w, variant, B, B * 11, stream_id=5)
         np.testing.assert_array_equal(anc, ref, err_msg=f"{variant} n={n} B={B}")
