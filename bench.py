@@ -231,6 +231,38 @@ def ceiling_section(torch, mgp):
             "hbm_read_GBs": hbm}
 
 
+def pattern_ceiling(torch, mgp, n, steps):
+    """The ceiling the Megopolis loop's own access pattern sets: its candidate
+    reads over a mirrored array of 2n + 1024 floats (the 4n-byte weights
+    twice) at `steps` shared offsets, without random draws or accept steps
+    (mgp_probe_pattern_read); median of 5 launches after one warm-up. Rate =
+    4 n steps bytes / time."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mirror = torch.rand(2 * n + 1024, dtype=torch.float32, device=dev)
+    offs = torch.from_numpy(np.random.Generator(np.random.PCG64(2109)).integers(0, n, steps).astype(np.uint32)
+                            .view(np.int32)).to(dev)
+    sink = torch.empty(n // 1024, dtype=torch.float32, device=dev)
+    times = []
+    for k in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        mgp.mgp_probe_pattern_read(mirror.data_ptr(), mirror.numel() * 4, n, offs.data_ptr(), steps,
+                                   sink.data_ptr(), stream.cuda_stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if k:
+            times.append(a.elapsed_time(b))
+    del mirror, offs, sink
+    ms = float(np.median(times))
+    gbs = 4.0 * n * steps / (ms * 1e-3) / 1e9
+    log(f"[bench] Megopolis read pattern alone (n={n}, {steps} steps): {ms:.3f} ms, {gbs:.0f} GB/s")
+    return {"workload": f"mgp_probe_pattern_read: the four-particle Megopolis loop's candidate reads, n={n}, "
+                        f"{steps} steps, no draws or accept steps; median of 5 after one warm-up",
+            "n": n, "steps": steps, "ms": ms, "GBs": gbs}
+
+
 def batched_section(torch, mgp, inputs, runs, shape=None):
     """512 filters, N_f = round(2^U(10, 18)), y_f ~ U[0, 4], D = 4, Megopolis:
     one graph launch per run against the same filters as 512 per-filter
@@ -701,6 +733,10 @@ def main():
     ceil = None if args.no_ceiling else ceiling_section(torch, mgp)
     mall = ceil["infinity_cache_read_GBs"] if ceil else float("nan")
     hbm = ceil["hbm_read_GBs"] if ceil else float("nan")
+    pat = float("nan")
+    if ceil and n % 1024 == 0 and B >= 5:
+        ceil["megopolis_pattern_read"] = pattern_ceiling(torch, mgp, n, 5 * (B // 5))
+        pat = ceil["megopolis_pattern_read"]["GBs"]
     kernel = {"megopolis": f"k_megopolis_mirror<4, {d // 4 if d % 4 == 0 and d <= 16 else -1}>",
               }.get(args.variant, f"k_resample<{args.variant}>")
 
@@ -741,8 +777,11 @@ def main():
             "avg_launch_ms": fused_ms,
             "ceiling": {"infinity_cache_read_GBs": mall, "frac_of_infinity_cache_read": achieved / mall,
                         "hbm_read_GBs": hbm,
+                        "megopolis_pattern_read_GBs": pat, "frac_of_pattern_read": achieved / pat,
                         "what": "mgp_probe_stream_read in this run: the best streaming-read rate over buffers of "
-                                "64-256 MB (Infinity Cache resident) and at 1-2 GB (HBM)"},
+                                "64-256 MB (Infinity Cache resident) and at 1-2 GB (HBM); mgp_probe_pattern_read: "
+                                "the loop's candidate reads alone at this n and B rounded down to whole rounds "
+                                "of five steps"},
             "traffic": None,
             "traffic_what": "bytes past the L2 (TCC to fabric: Infinity Cache or HBM), calibrated FETCH_SIZE + "
                             "WRITE_SIZE per launch",
@@ -752,7 +791,8 @@ def main():
                       "ms": loop_ms, "bytes_formula": "4NB candidate weights", "bytes": loop_bytes,
                       "GBs": loop_bytes / (loop_ms * 1e-3) / 1e9,
                       "frac_of_hbm_peak": loop_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                      "frac_of_infinity_cache_read": loop_bytes / (loop_ms * 1e-3) / 1e9 / mall},
+                      "frac_of_infinity_cache_read": loop_bytes / (loop_ms * 1e-3) / 1e9 / mall,
+                      "frac_of_pattern_read": loop_bytes / (loop_ms * 1e-3) / 1e9 / pat},
         "unfused": {"ms_per_step": ms_u, "loop_ms": loop_ms, "gather_ms": float(np.mean(per_u["gather"])),
                     "gather_GBs": 4.0 * n * (2 * d + 1) / (float(np.mean(per_u["gather"])) * 1e-3) / 1e9,
                     "fused_saving_ms": ms_u - ms},

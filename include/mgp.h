@@ -522,7 +522,7 @@ int mgp_resample_prefix(const float* w_dev, int32_t n, int32_t method, uint64_t 
                         int32_t* ancestors_dev, mgp_stats* stats_dev, void* workspace_dev, size_t workspace_bytes,
                         void* stream);
 
-/* ---- memory-system probe -------------------------------------------------
+/* ---- memory-system probes ------------------------------------------------
  * The streaming-read rate of the device at one buffer size: the benchmark
  * reports it as the memory ceiling beside the accept loop's achieved rate
  * (the loop streams its mirrored weights from whichever level holds them).
@@ -536,6 +536,20 @@ int mgp_resample_prefix(const float* w_dev, int32_t n, int32_t method, uint64_t 
  * events on `stream`: rate = passes * bytes / time. */
 int mgp_probe_stream_read(const void* buf_dev, size_t bytes, int32_t passes, int32_t blocks, float* sink_dev,
                           void* stream);
+
+/* The Megopolis accept loop's read pattern without its arithmetic: the
+ * ceiling the loop's own access pattern sets. n particles, four per thread in
+ * blocks of 256 threads (n / 1024 blocks), read at each of `steps` steps the
+ * candidate that Algorithm 5's segment arithmetic gives for the step's offset
+ * offsets_dev[b] (steps uint32 values, device; values >= n are clamped to
+ * n - 1), from mirror_dev, a mirrored array of at least 2n + 1024 floats
+ * (mirror_bytes), in rounds of five steps whose loads are issued together.
+ * No random draws and no accept steps. Rate = 4 n steps bytes / time.
+ * sink_dev: n / 1024 floats, written only if a block's sum of what it read
+ * is negative (never, for non-negative contents). n: a multiple of 1024, at
+ * most 2^29 (MGP_ERANGE above); steps: a positive multiple of 5. */
+int mgp_probe_pattern_read(const float* mirror_dev, size_t mirror_bytes, uint32_t n, const uint32_t* offsets_dev,
+                           int32_t steps, float* sink_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -187,6 +187,8 @@ def lib():
         L.mgp_resample_prefix.restype = ctypes.c_int
         L.mgp_probe_stream_read.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
         L.mgp_probe_stream_read.restype = ctypes.c_int
+        L.mgp_probe_pattern_read.argtypes = [_vp, ctypes.c_size_t, ctypes.c_uint32, _vp, ctypes.c_int32, _vp, _vp]
+        L.mgp_probe_pattern_read.restype = ctypes.c_int
         L.mgp_last_error.argtypes = []
         L.mgp_last_error.restype = ctypes.c_char_p
         L.mgp_version.argtypes = []
@@ -433,6 +435,12 @@ def mgp_resample_prefix(w_dev: int, n: int, method: int, seed: int, stream_id: i
 def mgp_probe_stream_read(buf_dev: int, nbytes: int, passes: int, blocks: int, sink_dev: int, stream: int) -> None:
     _check(lib().mgp_probe_stream_read(buf_dev, nbytes, passes, blocks, sink_dev, stream or None),
            "mgp_probe_stream_read")
+
+
+def mgp_probe_pattern_read(mirror_dev: int, mirror_bytes: int, n: int, offsets_dev: int, steps: int, sink_dev: int,
+                           stream: int) -> None:
+    _check(lib().mgp_probe_pattern_read(mirror_dev, mirror_bytes, n, offsets_dev, steps, sink_dev, stream or None),
+           "mgp_probe_pattern_read")
 
 
 # ---------------------------------------------------------------------------

@@ -119,6 +119,24 @@ def test_noalloc_size_limit_checked_on_the_host(mgp):
     assert e.value.code == mgp.MGP_EINVAL
 
 
+def test_probe_argument_errors_before_any_device_call(mgp):
+    """The memory probes check their arguments on the host (the pointers are
+    never dereferenced when a check fails)."""
+    n = 1 << 20
+    ok = 4 * (2 * n + 1024)
+    for args, code in [((0, ok, n, 16, 10, 16), mgp.MGP_EINVAL),        # NULL mirror
+                       ((16, ok, n + 5, 16, 10, 16), mgp.MGP_EINVAL),   # n not a multiple of 1024
+                       ((16, ok, n, 16, 7, 16), mgp.MGP_EINVAL),        # steps not a multiple of 5
+                       ((16, ok - 4, n, 16, 10, 16), mgp.MGP_EINVAL),   # mirror too small
+                       ((16, 1 << 33, 1 << 30, 16, 10, 16), mgp.MGP_ERANGE)]:  # n above 2^29
+        with pytest.raises(mgp.MgpError) as e:
+            mgp.mgp_probe_pattern_read(*args, 0)
+        assert e.value.code == code, (args, mgp.mgp_last_error())
+    with pytest.raises(mgp.MgpError) as e:
+        mgp.mgp_probe_stream_read(16, 24, 1, 1, 16, 0)  # bytes not a multiple of 16
+    assert e.value.code == mgp.MGP_EINVAL
+
+
 def test_version(mgp):
     assert mgp.mgp_version() >= 100
 
