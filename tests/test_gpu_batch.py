@@ -80,6 +80,29 @@ def test_small_ragged_batch_matches_oracle_and_separate(env, variant):
     plan.close()
 
 
+@pytest.mark.parametrize("variant,sched", [("metropolis", 1), ("c1", 1), ("c2", 1), ("c1", 2), ("c2", 2)])
+def test_explicit_B_at_every_block_edge(env, variant, sched):
+    """One filter per explicit B whose remainder mod 20 puts the chain's
+    partial last block at every four-step generator group edge (4, 8, 12,
+    16), inside a group (1, 3, 7, 19) and at whole blocks (20, 40), with the
+    grid and the persistent schedules."""
+    torch, dev, mgp = env
+    Bs = [1, 3, 4, 7, 8, 12, 16, 19, 20, 24, 28, 32, 36, 40, 41]
+    sizes = [3000 + 37 * f for f in range(len(Bs))]
+    ys = np.linspace(0.5, 3.5, len(Bs))
+    seeds = [900 + f for f in range(len(Bs))]
+    fl, hosts = make_filters(torch, dev, sizes, ys, 2, seeds, Bs=Bs)
+    plan = mgp.BatchPlan(fl, variant, d=2, block_threads=256, particles_per_thread=1, schedule=sched)
+    plan.run()
+    got = snapshot(torch, fl)
+    for f, (w, st) in enumerate(hosts):
+        ref = oracle.resample(w, variant, Bs[f], seeds[f], stream_id=f)
+        np.testing.assert_array_equal(got[f][0], ref, err_msg=f"{variant} B={Bs[f]}")
+        if got[f][1] is not None:
+            np.testing.assert_array_equal(got[f][1], oracle.gather(st, ref))
+    plan.close()
+
+
 @pytest.mark.parametrize("shape", [(256, 4, 1), (256, 2, 1), (256, 1, 1), (128, 4, 1), (128, 2, 2), (64, 4, 2),
                                    (256, 4, 2)])
 def test_megopolis_launch_shapes_agree(env, shape):
