@@ -37,6 +37,24 @@ def test_m_outputs_match_oracle(env, variant, n):
         np.testing.assert_array_equal(anc.cpu().numpy(), ref, err_msg=f"{variant} n={n} m={m}")
 
 
+@pytest.mark.parametrize("variant", ["megopolis", "metropolis", "c1", "c2"])
+def test_m_outputs_fixed_B_at_block_edges(env, variant):
+    """Fixed B whose remainder puts the generic chain's partial last block
+    inside and at the edges of its generator groups (5-step u groups for
+    Megopolis, 4-step j groups of 20-step blocks for the others), m above and
+    below n."""
+    torch, dev, mgp = env
+    n = 3001
+    w = inputs.gaussian_weights(n, 1.5, 8)
+    wd = torch.from_numpy(w).to(dev)
+    r = mgp.Resampler(n)
+    for B in (2, 4, 8, 9, 16, 24, 36, 43):
+        for m in (2 * n + 5, n - 100):
+            anc = r.resample_m(wd, m, variant, B=B, seed=70 + B, stream_id=3)
+            ref = oracle.resample_m(w, m, variant, B, 70 + B, stream_id=3)
+            np.testing.assert_array_equal(anc.cpu().numpy(), ref, err_msg=f"{variant} B={B} m={m}")
+
+
 @pytest.mark.parametrize("variant", ["megopolis", "metropolis"])
 def test_m_equal_n_is_resample(env, variant):
     torch, dev, mgp = env
